@@ -1,0 +1,180 @@
+"""Throughput of the exact filtered velocity + subgrid stress path on one GPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one exact-stress evaluation (filtered velocity, the six stress
+components and their plane averages) of one 192 x 129 x 192 channel
+snapshot; four seeded snapshots stay resident in HBM and are cycled. The
+timed region is K steps bracketed by device synchronisations; HIP events on
+the library's stream time every pass inside it. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "points/s for filt(u_i)+tau_ij filtering; MLP-closure speedup at stated tau error"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VALU_PEAK_TF = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, packed FP32 off
+FP32_MFMA_PEAK_TF = 157.3      # dense FP32 matrix rate
+BF16_MFMA_PEAK_TF = 2500.0     # dense BF16 matrix rate
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="dns192")
+    p.add_argument("--ygemm", default="fp32", choices=["fp32", "bf16", "bf16x3"])
+    p.add_argument("--tail", type=float, default=1e-8)
+    p.add_argument("--snapshots", type=int, default=4)
+    p.add_argument("--cpu-seconds", type=float, default=12.0,
+                   help="budget of the oracle CPU baseline (0 disables it)")
+    return p.parse_args()
+
+
+def pass_model(cfg, f, ops_nnz):
+    """Algorithmic flops and bytes per grid point of each pass."""
+    mx, mz = f.layout.mx, f.layout.mz
+    return {
+        # read u (3 x 4 B), write nine x/z-filtered fields (9 x 4 B);
+        # 9 fields x (x taps + z taps) FMAs + 7 flops forming u1' and the products
+        "xz": dict(bytes=48.0, flops=2.0 * 9 * ((2 * mx + 1) + (2 * mz + 1)) + 7.0),
+        # read nine fields, write 3 ubar + 6 tau; 12 banded operator products
+        "y": dict(bytes=72.0, flops=2.0 * 12 * ops_nnz + 12.0),
+    }
+
+
+def cpu_baseline(cfg, u_host, budget_s):
+    """The FP64 oracle timed on the host cores over whole snapshots."""
+    from threadpoolctl import threadpool_info
+    import numpy as np
+    from oracle import filter_ref as R
+    ops = R.Operators.from_config(cfg)
+    u64 = u_host.astype(np.float64)
+    reps, t0 = 0, time.perf_counter()
+    out = None
+    while True:
+        out = R.sgs_stress(u64, ops)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 8:
+            break
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    return {"value": cfg.points * reps / el, "unit": "points/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{reps} full {cfg.nx}x{cfg.ny}x{cfg.nz} snapshot(s), FP64 dense sums, {el:.1f} s"}, out
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
+              "(snapshots are independent: run one process per GPU)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1902_02508_amd import eles, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = synth.config(a.workload)
+    seeds = synth.SEEDS.get(a.workload, [0, 1, 2, 3])[: a.snapshots]
+    while len(seeds) < a.snapshots:
+        seeds.append(seeds[-1] + 1)
+    hosts, us = [], []
+    for s in seeds:
+        y, u = synth.make_snapshot(cfg, s)
+        hosts.append(u)
+        us.append(torch.from_numpy(u).to(dev))
+    f = eles.Filter.from_config(cfg, tail_tol=a.tail, ygemm=a.ygemm, device=dev)
+    ns = len(us)
+    ubar = [torch.empty((3,) + f.shape, dtype=torch.float32, device=dev) for _ in range(ns)]
+    tau = [torch.empty((6,) + f.shape, dtype=torch.float32, device=dev) for _ in range(ns)]
+    stats = [torch.empty((9, cfg.ny), dtype=torch.float64, device=dev) for _ in range(ns)]
+
+    def step(i):
+        k = i % ns
+        f.sgs_stress(us[k], ubar[k], tau[k], stats[k])
+
+    for i in range(a.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    print(f"warmup done ({a.warmup} steps)", file=sys.stderr, flush=True)
+
+    eles.filter_profile_begin(f.h, a.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        step(i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = eles.filter_profile_end(f.h)
+    el = t1 - t0
+    ms_per_step = 1e3 * el / a.steps
+    value = cfg.points * a.steps / el
+    print(f"timed {a.steps} steps: {ms_per_step:.4f} ms/step", file=sys.stderr, flush=True)
+
+    ops = f.operators()
+    nnz = float(np.count_nonzero(ops["wp"])) / cfg.ny
+    model = pass_model(cfg, f, nnz)
+    passes = {k: {"us_avg": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in prof.items()}
+    dom = max(("xz", "y"), key=lambda k: prof[k][0])
+    t_dom = prof[dom][0] / 1e3 / max(prof[dom][1], 1)
+    bytes_l = model[dom]["bytes"] * cfg.points
+    flops_l = model[dom]["flops"] * cfg.points
+    gbs = bytes_l / t_dom / 1e9
+    if dom == "xz":
+        tfs = flops_l / t_dom / 1e12
+        frac_alu, frac_hbm = tfs / FP32_VALU_PEAK_TF, gbs / HBM_PEAK_GBS
+        if frac_alu >= frac_hbm:
+            roof = {"bound": "alu", "achieved": tfs, "peak": FP32_VALU_PEAK_TF, "unit": "TFLOP/s",
+                    "frac": frac_alu}
+        else:
+            roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": frac_hbm}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS}
+    roof["kernel"] = "k_xz (x/z stencils + products)" if dom == "xz" else "k_y (y operator on MFMA + stress)"
+    roof["traffic"] = None
+
+    cpu = None
+    parity = None
+    if a.cpu_seconds > 0:
+        cpu, (rub, rtau) = cpu_baseline(cfg, hosts[0], a.cpu_seconds)
+        from oracle import filter_ref as R
+        f.sgs_stress(us[0], ubar[0], tau[0], stats[0])
+        torch.cuda.synchronize()
+        yv = synth.ygrid(cfg.ny, cfg.ykind, cfg.stretch)
+        gu = ubar[0].cpu().numpy().astype(np.float64)
+        gt = tau[0].cpu().numpy().astype(np.float64)
+        parity = max([R.rel_l2(gu[k], rub[k], yv) for k in range(3)] +
+                     [R.rel_l2(gt[k], rtau[k], yv) for k in range(6)])
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32" if a.ygemm == "fp32" else a.ygemm, "data": "synthetic",
+        "config": {"workload": f"channel {cfg.nx}x{cfg.ny}x{cfg.nz} exact filtered velocity + tau_ij",
+                   "box": f"{cfg.lx:.4f}x2x{cfg.lz:.4f}", "widths": [cfg.delta_x, cfg.delta_y, cfg.delta_z],
+                   "tail_tol": a.tail, "ygemm": a.ygemm, "snapshots": ns,
+                   "stencil_half_widths": [f.layout.mx, f.layout.mz], "parallelism": "none"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "passes": passes,
+        "max_rel_l2_vs_oracle": parity,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * eles.h - C ABI of the MI355X explicit-filter library.
+ *
+ * The library computes, on one gfx950 GPU, the explicit filter of eq. (2)
+ * of Bae & Lozano-Duran, "DNS-aided explicitly filtered LES of channel
+ * flow" (Sec. 2.1), with a kernel of constant width in all three
+ * directions, periodic in x and z and applied in y to the flow extended
+ * across both walls as in eq. (7) (Sec. 2.2); and the exact subgrid stress
+ * of the four-step procedure of Sec. 2.1,
+ *     tau_ij = F(u_i u_j) - F(u_i) F(u_j),
+ * with the filtered DNS velocity standing in for the discretised LES
+ * velocity (LES grid = DNS grid).
+ *
+ * Filter. The kernel is the separable Gaussian g_D(r) =
+ * sqrt(6/(pi D^2)) exp(-6 r^2 / D^2) per direction; its variance D^2/12 is
+ * the second moment of a top hat of width D (the equal-second-moment rule
+ * of Sec. 3). Eq. (2) is discretised by quadrature on the grid nodes:
+ * rectangle rule in x and z (with periodic images), trapezoid rule on the
+ * wall-normal nodes of the reflected, period-4 extended line; every output
+ * node's weights are normalised to sum to one. Kernel values below
+ * max(tail_tol, 1e-17) times the peak are dropped before normalisation.
+ * Fields of odd parity (u2, u1u2, u2u3) are reflected with a sign change
+ * and are treated as zero at the walls (eqs. (8) and (11)).
+ *
+ * Data layout. Every field is FP32, [nx][ny][nz] row-major (z fastest),
+ * with grid nodes x_i = i lx/nx, y_j = y[j], z_k = k lz/nz. A stack of
+ * fields is [nfields][nx][ny][nz]. Velocity stacks are (u1, u2, u3) =
+ * (streamwise, wall-normal, spanwise); stress stacks hold
+ * (tau11, tau12, tau13, tau22, tau23, tau33).
+ *
+ * Ownership. The caller allocates every device buffer (state, workspace,
+ * inputs, outputs) and keeps it alive while work that uses it is queued.
+ * The library never allocates device memory. Handles are host objects;
+ * *_destroy frees host memory only.
+ *
+ * Execution. Every call enqueues work on the given stream and returns
+ * without waiting for it, except filter_setup, which also copies the host
+ * y array to the device. One handle must not be used from two streams or
+ * threads at once. All device pointers must be 16-byte aligned.
+ *
+ * Errors. Arguments are validated before anything is enqueued; a failing
+ * call returns a non-zero eles_status and enqueues nothing. A HIP error
+ * at launch returns ELES_EHIP. No exception crosses the ABI.
+ */
+#ifndef ELES_H
+#define ELES_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ELES_OK = 0,
+  ELES_EINVAL = 1,    /* invalid argument: sizes, grid, widths, pointers   */
+  ELES_ENOSPACE = 2,  /* state or workspace smaller than required          */
+  ELES_EHIP = 3,      /* a HIP call or kernel launch failed                 */
+  ELES_ENUMERIC = 4,  /* a normalisation would underflow or overflow        */
+  ELES_ENOTSUP = 5    /* valid but outside what the kernels support         */
+} eles_status;
+
+/* Arithmetic of the wall-normal operator product (the y-pass). */
+typedef enum {
+  ELES_YGEMM_FP32 = 0,   /* FP32 operands on the matrix cores, FP32 sums      */
+  ELES_YGEMM_BF16 = 1,   /* operator and field rounded to BF16, FP32 sums     */
+  ELES_YGEMM_BF16X3 = 2  /* hi/lo BF16 split of both, three products, FP32    */
+} eles_ygemm;
+
+typedef struct {
+  int32_t nx, ny, nz;     /* nx, nz >= 1; ny >= 3                               */
+  double lx, lz;          /* periodic lengths, > 0                              */
+  const double *y;        /* host, ny values, strictly increasing,
+                             y[0] = -1 and y[ny-1] = +1 exactly (the walls)     */
+  double delta_x, delta_y, delta_z;   /* filter widths D, > 0                   */
+  double tail_tol;        /* in [0, 1e-2]; 0 keeps the kernel down to 1e-17     */
+  int32_t ygemm;          /* eles_ygemm                                         */
+} eles_filter_desc;
+
+typedef struct eles_filter_s *eles_filter;
+
+/* Byte offsets of the operators inside the device state (for inspection). */
+typedef struct {
+  int32_t mx, mz;          /* half-widths of the x and z stencils             */
+  int32_t ny_pad_m;        /* rows of the padded y operators (multiple of 16) */
+  int32_t ny_pad_k;        /* columns of the padded y operators (mult. of 32) */
+  size_t off_wp64, off_wm64;   /* FP64 [ny][ny] W^+ and W^-                   */
+  size_t off_wx64, off_wz64;   /* FP64 [2m+1] taps for offsets -m..m          */
+  size_t off_y64;              /* FP64 [ny] copy of y                          */
+  size_t off_shift;            /* FP64 [3][ny]: m, M = W^+ m, W^+ m^2 - M^2
+                                  of the last sgs_stress call                  */
+  size_t state_bytes;
+} eles_state_layout;
+
+/* Human-readable name of a status code. Never NULL. */
+const char *eles_status_string(int32_t status);
+
+/* Device bytes the state of this descriptor needs; 0 if the descriptor is
+ * invalid. */
+size_t filter_state_bytes(const eles_filter_desc *desc);
+
+/* Build the filter operators (Sec. 2.1 eq. (2) with the Sec. 2.2 wall
+ * extension) on the device, in FP64, into the caller's state buffer.
+ * desc->y is copied; the descriptor may be freed after the call. On success
+ * *out receives a new handle. Errors: EINVAL (descriptor, null pointers),
+ * ENOSPACE (state_bytes too small), ENUMERIC (width underflow), ENOTSUP
+ * (stencil half-width above the kernels' limit), EHIP. */
+int32_t filter_setup(const eles_filter_desc *desc, void *state, size_t state_bytes,
+                     hipStream_t stream, eles_filter *out);
+
+/* Choose the y-pass arithmetic (eles_ygemm) for later calls. */
+int32_t filter_set_ygemm(eles_filter f, int32_t ygemm);
+
+/* Operator layout of the handle's state. */
+int32_t filter_state_layout(eles_filter f, eles_state_layout *out);
+
+/* Workspace bytes of filter_fields with nfields fields. */
+size_t filter_workspace_bytes(eles_filter f, int32_t nfields);
+
+/* Workspace bytes of sgs_stress. */
+size_t sgs_workspace_bytes(eles_filter f);
+
+/* out[k] = F^(s_k)(in[k]) for k < nfields: eq. (2) with parity
+ * s_k = parity[k] in {+1, -1} under the eq. (7) reflection (host array).
+ * in, out: device [nfields][nx][ny][nz]; they must not overlap. Errors:
+ * EINVAL, ENOSPACE, EHIP. */
+int32_t filter_fields(eles_filter f, const float *in, int32_t nfields,
+                      const int8_t *parity, float *out, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/* Filtered velocity and exact subgrid stress (Sec. 2.1, four steps).
+ * u: device [3][nx][ny][nz]; ubar: device [3][...] = F(u_i) with parities
+ * (+, -, +); tau: device [6][...] = F(u_i u_j) - F(u_i) F(u_j), product
+ * parities s_i s_j. stats: device FP64 [9][ny] plane averages over x and z
+ * (Sec. 4.1) of ubar_1..3 then tau_11..33, or NULL. Internally u1 is
+ * shifted by a y-profile sampled from u1 before the products are formed,
+ * which leaves the exact result unchanged and removes most cancellation.
+ * u must not overlap ubar or tau. Errors: EINVAL, ENOSPACE, EHIP. */
+int32_t sgs_stress(eles_filter f, const float *u, float *ubar, float *tau,
+                   double *stats, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Per-pass GPU timing of later sgs_stress / filter_fields calls on this
+ * handle, with HIP events recorded on the call's stream around every
+ * kernel. Passes: 0 shift profile and correction operators, 1 x/z pass,
+ * 2 y pass, 3 plane statistics. filter_profile_begin creates events for up
+ * to max_calls calls (host-side HIP events; no device memory). After the
+ * timed calls, filter_profile_end waits for the last event and returns, per
+ * pass, the summed milliseconds and the number of launches timed, then
+ * releases the events. Errors: EINVAL, EHIP. */
+#define ELES_NPASS 4
+int32_t filter_profile_begin(eles_filter f, int32_t max_calls);
+int32_t filter_profile_end(eles_filter f, double *ms /* [ELES_NPASS] */,
+                           int32_t *launches /* [ELES_NPASS] */);
+
+void filter_destroy(eles_filter f);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELES_H */

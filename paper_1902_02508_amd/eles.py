@@ -1,0 +1,264 @@
+"""ctypes binding of the C ABI in include/eles.h (argument marshalling only).
+
+The functions keep the C names. ``Filter`` is a small convenience wrapper
+that allocates the caller-owned state and workspace as torch tensors on the
+current device and passes torch's current stream; every step of the
+computation runs in the HIP library. If ``libeles.so`` is missing the import
+of this module fails: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # load torch's HIP runtime first so the library binds to the same one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeles.so")
+
+ELES_OK, ELES_EINVAL, ELES_ENOSPACE, ELES_EHIP, ELES_ENUMERIC, ELES_ENOTSUP = range(6)
+YGEMM = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+
+
+class FilterDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("lx", ctypes.c_double), ("lz", ctypes.c_double),
+        ("y", ctypes.POINTER(ctypes.c_double)),
+        ("delta_x", ctypes.c_double), ("delta_y", ctypes.c_double), ("delta_z", ctypes.c_double),
+        ("tail_tol", ctypes.c_double),
+        ("ygemm", ctypes.c_int32),
+    ]
+
+
+class StateLayout(ctypes.Structure):
+    _fields_ = [
+        ("mx", ctypes.c_int32), ("mz", ctypes.c_int32),
+        ("ny_pad_m", ctypes.c_int32), ("ny_pad_k", ctypes.c_int32),
+        ("off_wp64", ctypes.c_size_t), ("off_wm64", ctypes.c_size_t),
+        ("off_wx64", ctypes.c_size_t), ("off_wz64", ctypes.c_size_t),
+        ("off_y64", ctypes.c_size_t), ("off_shift", ctypes.c_size_t),
+        ("state_bytes", ctypes.c_size_t),
+    ]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1902_02508_amd.build")
+lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_S = ctypes.c_size_t
+_I = ctypes.c_int32
+_SIG = {
+    "eles_status_string": (ctypes.c_char_p, [_I]),
+    "filter_state_bytes": (_S, [ctypes.POINTER(FilterDesc)]),
+    "filter_setup": (_I, [ctypes.POINTER(FilterDesc), _P, _S, _P, ctypes.POINTER(_P)]),
+    "filter_set_ygemm": (_I, [_P, _I]),
+    "filter_state_layout": (_I, [_P, ctypes.POINTER(StateLayout)]),
+    "filter_workspace_bytes": (_S, [_P, _I]),
+    "sgs_workspace_bytes": (_S, [_P]),
+    "filter_fields": (_I, [_P, _P, _I, _P, _P, _P, _S, _P]),
+    "sgs_stress": (_I, [_P, _P, _P, _P, _P, _P, _S, _P]),
+    "filter_profile_begin": (_I, [_P, _I]),
+    "filter_profile_end": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)]),
+    "filter_destroy": (None, [_P]),
+}
+for _name, (_res, _args) in _SIG.items():
+    _fn = getattr(lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTS = tuple(_SIG)
+
+
+class ElesError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {lib.eles_status_string(status).decode()} ({status})")
+
+
+def _check(status: int, where: str):
+    if status != ELES_OK:
+        raise ElesError(status, where)
+
+
+# ---- the C functions under their own names -----------------------------
+
+def eles_status_string(status: int) -> str:
+    return lib.eles_status_string(status).decode()
+
+
+def filter_state_bytes(desc: FilterDesc) -> int:
+    return lib.filter_state_bytes(ctypes.byref(desc))
+
+
+def filter_setup(desc, state_ptr, state_bytes, stream) -> _P:
+    h = _P()
+    _check(lib.filter_setup(ctypes.byref(desc), state_ptr, state_bytes, stream, ctypes.byref(h)), "filter_setup")
+    return h
+
+
+def filter_set_ygemm(h, ygemm: int):
+    _check(lib.filter_set_ygemm(h, ygemm), "filter_set_ygemm")
+
+
+def filter_state_layout(h) -> StateLayout:
+    out = StateLayout()
+    _check(lib.filter_state_layout(h, ctypes.byref(out)), "filter_state_layout")
+    return out
+
+
+def filter_workspace_bytes(h, nfields: int) -> int:
+    return lib.filter_workspace_bytes(h, nfields)
+
+
+def sgs_workspace_bytes(h) -> int:
+    return lib.sgs_workspace_bytes(h)
+
+
+def filter_fields(h, in_ptr, nfields, parity_ptr, out_ptr, ws_ptr, ws_bytes, stream):
+    _check(lib.filter_fields(h, in_ptr, nfields, parity_ptr, out_ptr, ws_ptr, ws_bytes, stream), "filter_fields")
+
+
+def sgs_stress(h, u_ptr, ubar_ptr, tau_ptr, stats_ptr, ws_ptr, ws_bytes, stream):
+    _check(lib.sgs_stress(h, u_ptr, ubar_ptr, tau_ptr, stats_ptr, ws_ptr, ws_bytes, stream), "sgs_stress")
+
+
+NPASS = 4
+PASS_NAMES = ("shift", "xz", "y", "stats")
+
+
+def filter_profile_begin(h, max_calls: int):
+    _check(lib.filter_profile_begin(h, max_calls), "filter_profile_begin")
+
+
+def filter_profile_end(h):
+    """{pass name: (total ms, launches)} of the calls timed since begin."""
+    ms = (ctypes.c_double * NPASS)()
+    n = (_I * NPASS)()
+    _check(lib.filter_profile_end(h, ms, n), "filter_profile_end")
+    return {PASS_NAMES[p]: (ms[p], n[p]) for p in range(NPASS)}
+
+
+def filter_destroy(h):
+    lib.filter_destroy(h)
+
+
+# ---- convenience wrapper -------------------------------------------------
+
+def make_desc(nx, ny, nz, lx, lz, y, delta_x, delta_y, delta_z, tail_tol=0.0, ygemm="fp32"):
+    """FilterDesc plus the host y array it points to (keep both alive)."""
+    yarr = np.ascontiguousarray(np.asarray(y, dtype=np.float64))
+    d = FilterDesc(int(nx), int(ny), int(nz), float(lx), float(lz),
+                   yarr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                   float(delta_x), float(delta_y), float(delta_z), float(tail_tol),
+                   YGEMM[ygemm] if isinstance(ygemm, str) else int(ygemm))
+    return d, yarr
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Filter:
+    """A filter handle with its state allocated on the current CUDA (HIP) device."""
+
+    def __init__(self, nx, ny, nz, lx, lz, y, delta_x, delta_y, delta_z,
+                 tail_tol=0.0, ygemm="fp32", device="cuda"):
+        self.shape = (int(nx), int(ny), int(nz))
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        desc, self._y = make_desc(nx, ny, nz, lx, lz, y, delta_x, delta_y, delta_z, tail_tol, ygemm)
+        nbytes = filter_state_bytes(desc)
+        if nbytes == 0:
+            raise ElesError(ELES_EINVAL, "filter_state_bytes")
+        self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.h = filter_setup(desc, _ptr(self.state), nbytes, _stream())
+        self.layout = filter_state_layout(self.h)
+        self._ws = torch.empty(0, dtype=torch.uint8, device=self.device)
+
+    @classmethod
+    def from_config(cls, cfg, tail_tol=0.0, ygemm="fp32", y=None, device="cuda"):
+        from .synth import ygrid
+        if y is None:
+            y = ygrid(cfg.ny, cfg.ykind, cfg.stretch)
+        return cls(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.lz, y,
+                   cfg.delta_x, cfg.delta_y, cfg.delta_z, tail_tol, ygemm, device)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            filter_destroy(h)
+            self.h = None
+
+    def set_ygemm(self, ygemm):
+        filter_set_ygemm(self.h, YGEMM[ygemm] if isinstance(ygemm, str) else int(ygemm))
+
+    def _workspace(self, nbytes):
+        if self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _field_check(self, t, n):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device != self.device:
+            raise ValueError("fields must be contiguous float32 tensors on the filter's device")
+        if tuple(t.shape) != (n,) + self.shape:
+            raise ValueError(f"expected shape {(n,) + self.shape}, got {tuple(t.shape)}")
+
+    def filter_fields(self, fields: torch.Tensor, parity: Sequence[int], out: Optional[torch.Tensor] = None):
+        nf = fields.shape[0]
+        self._field_check(fields, nf)
+        if out is None:
+            out = torch.empty_like(fields)
+        self._field_check(out, nf)
+        par = (ctypes.c_int8 * nf)(*[int(p) for p in parity])
+        nb = filter_workspace_bytes(self.h, nf)
+        ws = self._workspace(nb)
+        filter_fields(self.h, _ptr(fields), nf, ctypes.cast(par, ctypes.c_void_p), _ptr(out),
+                      _ptr(ws), ws.numel(), _stream())
+        return out
+
+    def sgs_stress(self, u: torch.Tensor, ubar=None, tau=None, stats=True):
+        self._field_check(u, 3)
+        if ubar is None:
+            ubar = torch.empty((3,) + self.shape, dtype=torch.float32, device=self.device)
+        if tau is None:
+            tau = torch.empty((6,) + self.shape, dtype=torch.float32, device=self.device)
+        self._field_check(ubar, 3)
+        self._field_check(tau, 6)
+        st = None
+        if stats is True:
+            st = torch.empty((9, self.shape[1]), dtype=torch.float64, device=self.device)
+        elif isinstance(stats, torch.Tensor):
+            st = stats
+        nb = sgs_workspace_bytes(self.h)
+        ws = self._workspace(nb)
+        sgs_stress(self.h, _ptr(u), _ptr(ubar), _ptr(tau), _ptr(st) if st is not None else None,
+                   _ptr(ws), ws.numel(), _stream())
+        return ubar, tau, st
+
+    def operators(self):
+        """FP64 operators copied back from the device state (for inspection)."""
+        L = self.layout
+        nx, ny, nz = self.shape
+        raw = self.state.cpu().numpy()
+
+        def f64(off, n):
+            return raw[off:off + 8 * n].view(np.float64).copy()
+        return {
+            "wp": f64(L.off_wp64, ny * ny).reshape(ny, ny),
+            "wm": f64(L.off_wm64, ny * ny).reshape(ny, ny),
+            "wx": f64(L.off_wx64, 2 * L.mx + 1),
+            "wz": f64(L.off_wz64, 2 * L.mz + 1),
+            "y": f64(L.off_y64, ny),
+            "shift": f64(L.off_shift, 3 * ny).reshape(3, ny),
+            "mx": L.mx, "mz": L.mz,
+        }

@@ -1,0 +1,104 @@
+"""The C ABI library loads, exports what include/eles.h declares, and rejects
+invalid arguments before touching the device (runs without a GPU)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "eles.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    src = re.sub(r"#[^\n]*", "", src)
+    names = []
+    for stmt in src.split(";"):
+        stmt = " ".join(stmt.split())
+        if "typedef" in stmt or "{" in stmt or "}" in stmt:
+            stmt = stmt.split("}")[-1]
+            if "typedef" in stmt:
+                continue
+        m = re.match(r"^(?:const\s+)?[A-Za-z_]\w*[\s\*]+([A-Za-z_]\w*)\s*\(", stmt.strip())
+        if m:
+            names.append(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def eles():
+    from paper_1902_02508_amd import eles as E
+    return E
+
+
+def test_header_declares_the_boundary():
+    names = set(declared_functions())
+    for must in ("filter_setup", "filter_fields", "sgs_stress", "filter_state_bytes",
+                 "filter_workspace_bytes", "sgs_workspace_bytes", "filter_destroy",
+                 "eles_status_string", "filter_state_layout", "filter_set_ygemm"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(eles):
+    for name in declared_functions():
+        assert hasattr(eles.lib, name), name
+        assert name in eles.EXPORTS, name
+
+
+def _desc(eles, **over):
+    y = np.cos(np.pi * np.arange(17)[::-1] / 16) * 1.0
+    y[0], y[-1] = -1.0, 1.0
+    kw = dict(nx=16, ny=17, nz=12, lx=2.0, lz=1.0, y=y, delta_x=0.3, delta_y=0.2, delta_z=0.2)
+    kw.update(over)
+    return eles.make_desc(**kw)
+
+
+def test_valid_descriptor_sizes(eles):
+    d, y = _desc(eles)
+    assert eles.filter_state_bytes(d) > 17 * 17 * 16
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(nx=0), 1), (dict(ny=2, y=np.array([-1.0, 1.0])), 1), (dict(lx=-1.0), 1),
+    (dict(lz=float("nan")), 1), (dict(delta_y=0.0), 1), (dict(delta_x=float("inf")), 1),
+    (dict(tail_tol=0.5), 1), (dict(ygemm=7), 1),
+    (dict(y=np.linspace(-1, 1, 17)[::-1].copy()), 1),             # decreasing
+    (dict(y=np.linspace(-1, 0.9, 17)), 1),                          # wall not at +1
+    (dict(y=np.concatenate([[-1.0], np.full(15, 0.0), [1.0]])), 1),  # repeated nodes
+    (dict(delta_y=1e-300), 4),                                     # width underflows
+    (dict(delta_x=50.0), 5),                                       # stencil too wide
+])
+def test_invalid_descriptors_rejected(eles, over, status):
+    d, y = _desc(eles, **over)
+    assert eles.filter_state_bytes(d) == 0
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(1 << 20)
+    aligned = (ctypes.addressof(buf) + 255) & ~255
+    st = eles.lib.filter_setup(ctypes.byref(d), aligned, 1 << 19, None, ctypes.byref(h))
+    assert st == status
+    assert not h.value
+
+
+def test_setup_rejects_bad_buffers_before_any_launch(eles):
+    d, y = _desc(eles)
+    n = eles.filter_state_bytes(d)
+    h = ctypes.c_void_p()
+    assert eles.lib.filter_setup(ctypes.byref(d), None, n, None, ctypes.byref(h)) == eles.ELES_EINVAL
+    assert eles.lib.filter_setup(ctypes.byref(d), 0x1003, n, None, ctypes.byref(h)) == eles.ELES_EINVAL
+    assert eles.lib.filter_setup(ctypes.byref(d), 0x1000, n - 1, None, ctypes.byref(h)) == eles.ELES_ENOSPACE
+    assert eles.lib.filter_setup(ctypes.byref(d), 0x1000, n, None, None) == eles.ELES_EINVAL
+
+
+def test_calls_on_null_handle_rejected(eles):
+    assert eles.lib.sgs_stress(None, 16, 16, 16, None, 16, 1 << 20, None) == eles.ELES_EINVAL
+    assert eles.lib.filter_fields(None, 16, 1, 16, 16, 16, 1 << 20, None) == eles.ELES_EINVAL
+    assert eles.lib.filter_workspace_bytes(None, 3) == 0
+    assert eles.lib.sgs_workspace_bytes(None) == 0
+    assert eles.lib.filter_set_ygemm(None, 0) == eles.ELES_EINVAL
+    for s in range(7):
+        assert eles.eles_status_string(s)
