@@ -38,7 +38,21 @@ def parse():
     p.add_argument("--snapshots", type=int, default=4)
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the oracle CPU baseline (0 disables it)")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run plain device-to-device copies of this many MiB "
+                        "(reference dispatches for scaling the HBM byte counters)")
     return p.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "dispatches": 3}))
 
 
 def pass_model(cfg, f, ops_nnz):
@@ -76,6 +90,9 @@ def cpu_baseline(cfg, u_host, budget_s):
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
               "(snapshots are independent: run one process per GPU)", file=sys.stderr)

@@ -16,7 +16,7 @@ struct eles_filter_s {
   int ygemm;
   eles::OpsView v;
   eles_state_layout lay;
-  int zt, nzt, nxt, n32;
+  int zt, nzt, nxt, n16;
   size_t npts;
   // per-pass event timing
   int prof_max = 0, prof_calls = 0;
@@ -135,7 +135,7 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 size_t sgs_ws(const eles_filter_s *f, size_t *off_part) {
   const size_t x = up256(9 * f->npts * sizeof(float));
   if (off_part) *off_part = x;
-  return x + up256((size_t)9 * f->d.ny * f->d.nx * f->n32 * sizeof(double));
+  return x + up256((size_t)9 * f->d.ny * eles::y_parts(f->d.nx, f->n16) * sizeof(double));
 }
 
 eles::YArgs y_args(const eles_filter_s *f) {
@@ -153,7 +153,7 @@ eles::YArgs y_args(const eles_filter_s *f) {
   a.nz = f->d.nz;
   a.mpad = f->v.mpad;
   a.kpad = f->v.kpad;
-  a.n32 = f->n32;
+  a.n16 = f->n16;
   return a;
 }
 
@@ -242,7 +242,7 @@ int32_t filter_setup(const eles_filter_desc *desc, void *state, size_t state_byt
   f->zt = eles::xz_tile_z(desc->nz, p.mz);
   f->nzt = (desc->nz + f->zt - 1) / f->zt;
   f->nxt = (desc->nx + eles::kXzTileX - 1) / eles::kXzTileX;
-  f->n32 = (desc->nz + eles::kYTileN - 1) / eles::kYTileN;
+  f->n16 = (desc->nz + eles::kYTileN - 1) / eles::kYTileN;
   eles_state_layout &L = f->lay;
   L.mx = p.mx;
   L.mz = p.mz;
@@ -302,13 +302,13 @@ int32_t filter_fields(eles_filter f, const float *in, int32_t nfields, const int
     xa.in = in + (size_t)g0 * n;
     xa.in_stride = n;
     xa.out = tmp;
-    xa.out_stride = n;
+    xa.out_nf = nc;
     xa.mshift = nullptr;
     xa.ncomp = nc;
     if (timed(f, 1, stream, [&] { return eles::launch_xz(xa, false, stream); }) != hipSuccess) return ELES_EHIP;
     eles::YArgs ya = y_args(f);
     ya.in = tmp;
-    ya.in_stride = n;
+    ya.in_nf = nc;
     ya.out = out + (size_t)g0 * n;
     ya.out_stride = n;
     ya.nfield = nc;
@@ -344,13 +344,13 @@ int32_t sgs_stress(eles_filter f, const float *u, float *ubar, float *tau, doubl
   xa.in = u;
   xa.in_stride = n;
   xa.out = X;
-  xa.out_stride = n;
+  xa.out_nf = 9;
   xa.mshift = f->v.prof32;
   xa.ncomp = 3;
   if (timed(f, 1, stream, [&] { return eles::launch_xz(xa, true, stream); }) != hipSuccess) return ELES_EHIP;
   eles::YArgs ya = y_args(f);
   ya.in = X;
-  ya.in_stride = n;
+  ya.in_nf = 9;
   ya.ubar = ubar;
   ya.tau = tau;
   ya.part = part;
@@ -358,7 +358,7 @@ int32_t sgs_stress(eles_filter f, const float *u, float *ubar, float *tau, doubl
   if (timed(f, 2, stream, [&] { return eles::launch_y(ya, true, f->ygemm, stream); }) != hipSuccess)
     return ELES_EHIP;
   if (stats) {
-    const int nparts = f->d.nx * f->n32;
+    const int nparts = eles::y_parts(f->d.nx, f->n16);
     const double inv = 1.0 / ((double)f->d.nx * f->d.nz);
     if (timed(f, 3, stream, [&] { return eles::launch_stats(part, stats, f->d.ny, nparts, inv, stream); }) !=
         hipSuccess)

@@ -15,7 +15,7 @@ constexpr int kXzRowPad = 16;     // LDS row padding of the x-filtered tile
 constexpr int kMaxHalfX = 128;    // largest x stencil half-width
 constexpr int kMaxHalfZ = 120;    // largest z stencil half-width: 2m + 8 <= 256
 constexpr int kYBlockM = 16;      // rows of one y-pass output tile
-constexpr int kYTileN = 32;       // columns (z) of one wave's y-pass tile
+constexpr int kYTileN = 16;       // columns (z) of one wave's y-pass tile
 constexpr int kYWaves = 4;        // waves per y-pass block
 constexpr int kKAlign = 32;       // column padding of the y operators
 constexpr int kMeanSlabs = 8;     // x-slabs sampled for the shift profile
@@ -52,8 +52,8 @@ hipError_t launch_shift_ops(const OpsView &v, const float *u1, hipStream_t s);
 struct XzArgs {
   const float *in;
   size_t in_stride;    // elements between input components
-  float *out;
-  size_t out_stride;   // elements between output fields
+  float *out;          // fields interleaved by row: [nx][ny][out_nf][nz]
+  int out_nf;
   const float *wx, *wz, *mshift;
   int nx, ny, nz, mx, mz, zt, nzt, nxt, ncomp;
 };
@@ -62,20 +62,22 @@ int xz_tile_z(int nz, int mz);
 
 // y pass, k_y.hip.
 struct YArgs {
-  const float *in;        // x/z-filtered fields
-  size_t in_stride;
+  const float *in;        // x/z-filtered fields, [nx][ny][in_nf][nz]
+  int in_nf;
   float *ubar, *tau;      // sgs outputs
   float *out;             // plain outputs
   size_t out_stride;
-  double *part;           // sgs plane partials [9][ny][nx*n32] or null
+  double *part;           // sgs plane partials [9][ny][y_parts()] or null
   const float *a32[4];
   const uint16_t *ahi[4], *alo[4];
   const int *rowband;
   const float *prof32;
-  int nx, ny, nz, mpad, kpad, n32, nfield;
+  int nx, ny, nz, mpad, kpad, n16, nfield;
   uint32_t parity_mask;   // plain: bit f set = field f odd
 };
 hipError_t launch_y(const YArgs &a, bool sgs, int prec, hipStream_t s);
+// Number of plane partials per (quantity, row) the stress y pass writes.
+inline int y_parts(int nx, int n16) { return nx * ((n16 + kYWaves - 1) / kYWaves); }
 hipError_t launch_stats(const double *part, double *stats, int ny, int nparts,
                         double inv_count, hipStream_t s);
 

@@ -10,7 +10,8 @@
 // velocity is read once and the products are never stored. The x-filtered
 // strip goes to LDS. Stage Z: each thread takes runs of eight z outputs of
 // one (field, x) row and applies the z stencil from LDS, writing coalesced
-// rows back to HBM.
+// rows back to HBM. The nine outputs are interleaved by row, [x][y][f][z],
+// so the y pass finds all fields of one (x, y) row side by side.
 //
 // Taps are read through uniform (scalar) loads from zero-padded tap arrays,
 // so the per-output loops carry no bounds tests.
@@ -56,15 +57,73 @@ struct Fields<false> {
   }
 };
 
+// Row-group modes of the streaming stencil loops. A group is four
+// consecutive input rows r0..r0+3 feeding XT outputs o through tap r - o.
+enum { G_HEAD = 0, G_FULL = 1, G_ANY = 2 };
+
+// Does input row r reach output o through a kept tap (0 <= r - o <= m2)?
+// HEAD groups start at a compile-time row below XT and never pass the far
+// end (m2 >= 8); FULL groups are inside the band for every o. Groups past
+// the band's far end also run as FULL: the padded tap arrays are zero
+// beyond offset m2, which costs a few multiplications by zero instead of a
+// branch per (row, output) pair. ANY tests both ends (narrow stencils).
+template <int MODE>
+__device__ inline bool reach(int r, int o, int m2) {
+  if (MODE == G_HEAD) return o <= r;
+  if (MODE == G_FULL) return true;
+  return o <= r && r - o <= m2;
+}
+
+template <bool SGS, int MODE, int R0>
+__device__ inline void x_group(float (&acc)[Fields<SGS>::NF][XT], const float (&cur)[4][3], float ms,
+                               const float *__restrict__ wx, int r0, int m2) {
+  constexpr int NF = Fields<SGS>::NF;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float c3[3] = {cur[k][0] - ms, cur[k][1], cur[k][2]};
+    float v[NF];
+    Fields<SGS>::form(c3, v);
+    const int r = (MODE == G_HEAD ? R0 : r0) + k;
+    const float *w = wx + (r + XT - 1);
+#pragma unroll
+    for (int o = 0; o < XT; ++o) {
+      if (!reach<MODE>(r, o, m2)) continue;
+      const float wt = w[-o];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) acc[f][o] = fmaf(wt, v[f], acc[f][o]);
+    }
+  }
+}
+
+template <int MODE, int T0>
+__device__ inline void z_group(float (&acc)[RZ], const float *src, const float *__restrict__ wz, int t4, int m2) {
+  const int tb = MODE == G_HEAD ? T0 : t4;
+  const float4 v = *reinterpret_cast<const float4 *>(src + tb);
+  const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int t = tb + k;
+    const float *w = wz + (t + RZ - 1);
+#pragma unroll
+    for (int q = 0; q < RZ; ++q) {
+      if (!reach<MODE>(t, q, m2)) continue;
+      acc[q] = fmaf(w[-q], vv[k], acc[q]);
+    }
+  }
+}
+
 template <bool SGS>
 __global__ void __launch_bounds__(kXzThreads)
 k_xz(XzArgs a, const float *__restrict__ gin, float *__restrict__ gout,
      const float *__restrict__ wx, const float *__restrict__ wz) {
   constexpr int NF = Fields<SGS>::NF;
-  extern __shared__ float tx[];   // [NF][XT][zs]
+  constexpr int NG = SGS ? 2 : 1;               // field groups staged through LDS
+  constexpr int GF = (NF + NG - 1) / NG;        // fields per group
+  extern __shared__ float tx[];                 // [GF][XT][zs]
   const int zh = a.zt + 2 * a.mz;
   const int zs = ((zh + 4 + 3) / 4) * 4;
   const int tid = threadIdx.x;
+  const int mx2 = 2 * a.mx, mz2 = 2 * a.mz;
 
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int xt = b % a.nxt;
@@ -72,95 +131,113 @@ k_xz(XzArgs a, const float *__restrict__ gin, float *__restrict__ gout,
   const int ztile = rest % a.nzt;
   const int y = rest / a.nzt;
   const int x0 = xt * XT, z0 = ztile * a.zt;
+  const size_t xstride = (size_t)a.ny * a.nz;
 
   // zero the row tails read by the last vector loads of stage Z
-  for (int q = tid; q < NF * XT * (zs - zh); q += kXzThreads) {
+  for (int q = tid; q < GF * XT * (zs - zh); q += kXzThreads) {
     int row = q / (zs - zh), col = zh + q % (zs - zh);
     tx[row * zs + col] = 0.0f;
   }
 
-  // ---- stage X
+  // ---- stage X: x-filtered values of every field for one column per thread
+  float acc[NF][XT];
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int o = 0; o < XT; ++o) acc[f][o] = 0.0f;
   if (tid < zh) {
     const int gz = wrap(z0 - a.mz + tid, a.nz);
     const float ms = SGS ? a.mshift[y] : 0.0f;
     const size_t plane = (size_t)y * a.nz + gz;
-    const size_t xstride = (size_t)a.ny * a.nz;
-    float acc[NF][XT];
+    // component bases; a missing component (plain mode, ncomp < 3) re-reads
+    // the last one so that every load is unconditional
+    const float *cb[3];
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-      for (int o = 0; o < XT; ++o) acc[f][o] = 0.0f;
-
-    const int rows = ((XT + 2 * a.mx) + 3) / 4 * 4;
+    for (int c = 0; c < 3; ++c) cb[c] = gin + (size_t)(c < a.ncomp ? c : a.ncomp - 1) * a.in_stride + plane;
     int gx = wrap(x0 - a.mx, a.nx);
-    float cur[4][3], nxt[4][3];
+    // rows arrive two groups ahead of their use
+    float cur[4][3], nx1[4][3], nx2[4][3];
     auto load_group = [&](float (&dst)[4][3]) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const size_t off = (size_t)gx * xstride + plane;
+        const size_t off = (size_t)gx * xstride;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          dst[k][c] = (c < a.ncomp) ? gin[c * a.in_stride + off] : 0.0f;
+        for (int c = 0; c < 3; ++c) dst[k][c] = cb[c][off];
         gx = (gx + 1 == a.nx) ? 0 : gx + 1;
       }
     };
-    load_group(cur);
-    for (int r0 = 0; r0 < rows; r0 += 4) {
-      if (r0 + 4 < rows) load_group(nxt);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        float c3[3] = {cur[k][0] - ms, cur[k][1], cur[k][2]};
-        float v[NF];
-        Fields<SGS>::form(c3, v);
-        const float *w = wx + (r0 + k + XT - 1);
-#pragma unroll
-        for (int o = 0; o < XT; ++o) {
-          const float wt = w[-o];
-#pragma unroll
-          for (int f = 0; f < NF; ++f) acc[f][o] = fmaf(wt, v[f], acc[f][o]);
-        }
-      }
+    auto advance = [&]() {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) cur[k][c] = nxt[k][c];
-    }
-#pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-      for (int o = 0; o < XT; ++o) tx[(f * XT + o) * zs + tid] = acc[f][o];
-  }
-  __syncthreads();
-
-  // ---- stage Z
-  const int nch = a.zt / RZ;
-  const int items = NF * XT * nch;
-  const int zrows = ((RZ + 2 * a.mz) + 3) / 4 * 4;
-  const size_t xstride = (size_t)a.ny * a.nz;
-  for (int it = tid; it < items; it += kXzThreads) {
-    const int c = it % nch;
-    const int row = it / nch;
-    const int f = row / XT, o = row % XT;
-    const int xg = x0 + o;
-    if (xg >= a.nx || f >= (SGS ? NF : a.ncomp)) continue;
-    const float *src = tx + row * zs + c * RZ;
-    float acc[RZ];
-#pragma unroll
-    for (int q = 0; q < RZ; ++q) acc[q] = 0.0f;
-    for (int t4 = 0; t4 < zrows; t4 += 4) {
-      const float4 v = *reinterpret_cast<const float4 *>(src + t4);
-      const float vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float *w = wz + (t4 + k + RZ - 1);
-#pragma unroll
-        for (int q = 0; q < RZ; ++q) acc[q] = fmaf(w[-q], vv[k], acc[q]);
+        for (int c = 0; c < 3; ++c) {
+          cur[k][c] = nx1[k][c];
+          nx1[k][c] = nx2[k][c];
+        }
+    };
+    const int rows = XT + mx2;
+    load_group(cur);
+    load_group(nx1);
+    if (mx2 >= XT) {
+      load_group(nx2);
+      x_group<SGS, G_HEAD, 0>(acc, cur, ms, wx, 0, mx2);
+      advance();
+      load_group(nx2);
+      x_group<SGS, G_HEAD, 4>(acc, cur, ms, wx, 4, mx2);
+      advance();
+      for (int r0 = XT; r0 < rows; r0 += 4) {
+        load_group(nx2);
+        x_group<SGS, G_FULL, 0>(acc, cur, ms, wx, r0, mx2);
+        advance();
+      }
+    } else {
+      for (int r0 = 0; r0 < rows; r0 += 4) {
+        load_group(nx2);
+        x_group<SGS, G_ANY, 0>(acc, cur, ms, wx, r0, mx2);
+        advance();
       }
     }
-    float *dst = gout + f * a.out_stride + (size_t)xg * xstride + (size_t)y * a.nz + z0 + c * RZ;
+  }
+
+  // ---- stage Z, one LDS field group at a time
+  const int nch = a.zt / RZ;
+  const int zrows = RZ + mz2;
 #pragma unroll
-    for (int q = 0; q < RZ; ++q)
-      if (c * RZ + q < a.zt && z0 + c * RZ + q < a.nz) dst[q] = acc[q];
+  for (int g = 0; g < NG; ++g) {
+    const int f0 = g * GF;
+    const int nfg = (NF - f0) < GF ? (NF - f0) : GF;
+    if (g > 0) __syncthreads();   // the previous group's readers are done
+    if (tid < zh) {
+#pragma unroll
+      for (int f = 0; f < GF; ++f)
+        if (f < nfg)
+#pragma unroll
+          for (int o = 0; o < XT; ++o) tx[(f * XT + o) * zs + tid] = acc[f0 + f][o];
+    }
+    __syncthreads();
+    const int items = nfg * XT * nch;
+    for (int it = tid; it < items; it += kXzThreads) {
+      const int c = it % nch;
+      const int row = it / nch;
+      const int f = f0 + row / XT, o = row % XT;
+      const int xg = x0 + o;
+      if (xg >= a.nx || f >= (SGS ? NF : a.ncomp)) continue;
+      const float *src = tx + row * zs + c * RZ;
+      float zacc[RZ];
+#pragma unroll
+      for (int q = 0; q < RZ; ++q) zacc[q] = 0.0f;
+      if (mz2 >= RZ) {
+        z_group<G_HEAD, 0>(zacc, src, wz, 0, mz2);
+        z_group<G_HEAD, 4>(zacc, src, wz, 4, mz2);
+        for (int t4 = RZ; t4 < zrows; t4 += 4) z_group<G_FULL, 0>(zacc, src, wz, t4, mz2);
+      } else {
+        for (int t4 = 0; t4 < zrows; t4 += 4) z_group<G_ANY, 0>(zacc, src, wz, t4, mz2);
+      }
+      float *dst = gout + (((size_t)xg * a.ny + y) * a.out_nf + f) * a.nz + z0 + c * RZ;
+#pragma unroll
+      for (int q = 0; q < RZ; ++q)
+        if (c * RZ + q < a.zt && z0 + c * RZ + q < a.nz) dst[q] = zacc[q];
+    }
   }
 }
 
@@ -176,8 +253,8 @@ int xz_tile_z(int nz, int mz) {
 hipError_t launch_xz(const XzArgs &a, bool sgs, hipStream_t s) {
   const int zh = a.zt + 2 * a.mz;
   const int zs = ((zh + 4 + 3) / 4) * 4;
-  const int nf = sgs ? 9 : 3;
-  const size_t lds = (size_t)nf * XT * zs * sizeof(float);
+  const int gf = sgs ? 5 : 3;   // fields per LDS group
+  const size_t lds = (size_t)gf * XT * zs * sizeof(float);
   const long nblk = (long)a.nxt * a.nzt * a.ny;
   if (lds > 65536) {
     hipError_t e = sgs ? hipFuncSetAttribute((const void *)k_xz<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)

@@ -3,8 +3,8 @@
 // every (x, z) line, on the matrix cores, fused with the stress epilogue.
 //
 // For an x-slab the fields form a [ny x nz] matrix (z contiguous); the
-// filtered slab is W^s times it. One wave computes a 16-row x 32-column
-// output tile with v_mfma_f32_16x16x4_f32 (FP32) or
+// filtered slab is W^s times it. One wave computes a 16 x 16 output
+// tile with v_mfma_f32_16x16x4_f32 (FP32) or
 // v_mfma_f32_16x16x32_bf16 (BF16, and the three-product hi/lo split). The
 // operator is banded: the K loop covers only the columns that are nonzero
 // in the tile's 16 rows.
@@ -102,209 +102,194 @@ k_y(YArgs a, const float *__restrict__ X, const int *__restrict__ rowband) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int nib = a.mpad / kYBlockM;
-  const long items = (long)a.nx * nib * a.n32;
+  // items (x, i-block, z-tile) with z fastest; the tile count is padded to
+  // a multiple of the block's waves so a block never straddles two rows
+  const int nzt = (a.n16 + kYWaves - 1) / kYWaves * kYWaves;
+  const long items = (long)a.nx * nib * nzt;
   const long item = (long)xcd_remap(blockIdx.x, gridDim.x) * kYWaves + wave;
-  if (item >= items) return;
-  const int zt = (int)(item % a.n32);
-  const long rest = item / a.n32;
+  const int zt = (int)(item % nzt);
+  const long rest = item / nzt;
   const int ib = (int)(rest % nib);
   const int x = (int)(rest / nib);
+  const bool live = item < items && zt < a.n16;
   const int i0 = ib * kYBlockM, z0 = zt * kYTileN;
   const int field = SGS ? 0 : blockIdx.y;
   const int opsel = SGS ? 0 : (int)((a.parity_mask >> field) & 1u);
+  const int zc = z0 + col;
+  const bool zok = live && zc < a.nz;
 
-  int klo, khi;
-  tile_band(rowband, i0, klo, khi);
+  int klo = 0, khi = 0;
+  if (live) tile_band(rowband, i0, klo, khi);
 
-  f4 acc[NA][2];
+  f4 acc[NA];
 #pragma unroll
-  for (int f = 0; f < NA; ++f)
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) acc[f][nt] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int f = 0; f < NA; ++f) acc[f] = f4{0.f, 0.f, 0.f, 0.f};
 
   const size_t slab = (size_t)x * a.ny;
-  const float *Xf = X + (SGS ? 0 : (size_t)field * a.in_stride);
+  const size_t rowst = (size_t)a.in_nf * a.nz;    // one (x, y) row of all fields
+  const float *Xf = X + (SGS ? 0 : (size_t)field * a.nz);
 
   if (PREC == 0) {
-    for (int k0 = klo & ~3; k0 < khi; k0 += 4) {
+    // B fragments arrive two K steps ahead of the matrix instructions
+    // that consume them.
+    float b[NA], bn[NA], bnn[NA];
+    auto load_b = [&](int k0, float (&dst)[NA]) {
       const int kk = k0 + grp;
-      const size_t ao = (size_t)(i0 + col) * a.kpad + kk;
-      const bool kv = kk < a.ny;
+      const bool ok = zok && kk < a.ny && k0 < khi;
+      const size_t off = (slab + (ok ? kk : 0)) * rowst + (ok ? zc : 0);
+#pragma unroll
+      for (int f = 0; f < NA; ++f) {
+        const float t = Xf[(size_t)f * a.nz + off];
+        dst[f] = ok ? t : 0.0f;
+      }
+    };
+    const int kb0 = klo & ~3;
+    load_b(kb0, b);
+    load_b(kb0 + 4, bn);
+    for (int k0 = kb0; k0 < khi; k0 += 4) {
+      load_b(k0 + 8, bnn);
+      const size_t ao = (size_t)(i0 + col) * a.kpad + k0 + grp;
       if (SGS) {
         const float ap = a.a32[0][ao], am = a.a32[1][ao];
         const float cp = a.a32[2][ao], cm = a.a32[3][ao];
-        const float cp2 = 2.0f * cp;
-        float b[2][9];
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-          const int zc = z0 + nt * 16 + col;
-          const bool ok = kv && zc < a.nz;
-          const size_t off = (slab + kk) * a.nz + zc;
-#pragma unroll
-          for (int f = 0; f < 9; ++f) b[nt][f] = ok ? Xf[f * a.in_stride + off] : 0.0f;
-        }
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-          acc[0][nt] = mma32(ap, b[nt][0], acc[0][nt]);
-          acc[3][nt] = mma32(cp2, b[nt][0], acc[3][nt]);
-          acc[1][nt] = mma32(am, b[nt][1], acc[1][nt]);
-          acc[4][nt] = mma32(cm, b[nt][1], acc[4][nt]);
-          acc[2][nt] = mma32(ap, b[nt][2], acc[2][nt]);
-          acc[5][nt] = mma32(cp, b[nt][2], acc[5][nt]);
-          acc[3][nt] = mma32(ap, b[nt][3], acc[3][nt]);
-          acc[4][nt] = mma32(am, b[nt][4], acc[4][nt]);
-          acc[5][nt] = mma32(ap, b[nt][5], acc[5][nt]);
-          acc[6][nt] = mma32(ap, b[nt][6], acc[6][nt]);
-          acc[7][nt] = mma32(am, b[nt][7], acc[7][nt]);
-          acc[8][nt] = mma32(ap, b[nt][8], acc[8][nt]);
-        }
+        acc[0] = mma32(ap, b[0], acc[0]);
+        acc[3] = mma32(2.0f * cp, b[0], acc[3]);
+        acc[1] = mma32(am, b[1], acc[1]);
+        acc[4] = mma32(cm, b[1], acc[4]);
+        acc[2] = mma32(ap, b[2], acc[2]);
+        acc[5] = mma32(cp, b[2], acc[5]);
+        acc[3] = mma32(ap, b[3], acc[3]);
+        acc[4] = mma32(am, b[4], acc[4]);
+        acc[5] = mma32(ap, b[5], acc[5]);
+        acc[6] = mma32(ap, b[6], acc[6]);
+        acc[7] = mma32(am, b[7], acc[7]);
+        acc[8] = mma32(ap, b[8], acc[8]);
       } else {
-        const float w = a.a32[opsel][ao];
+        acc[0] = mma32(a.a32[opsel][ao], b[0], acc[0]);
+      }
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-          const int zc = z0 + nt * 16 + col;
-          const bool ok = kv && zc < a.nz;
-          const float bv = ok ? Xf[(slab + kk) * a.nz + zc] : 0.0f;
-          acc[0][nt] = mma32(w, bv, acc[0][nt]);
-        }
+      for (int f = 0; f < NA; ++f) {
+        b[f] = bn[f];
+        bn[f] = bnn[f];
       }
     }
   } else {
     for (int k0 = klo & ~31; k0 < khi; k0 += 32) {
       const int kb = k0 + 8 * grp;
       const size_t ao = (size_t)(i0 + col) * a.kpad + kb;
+      auto load8 = [&](int f, float (&v)[8]) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = kb + e;
+          v[e] = (zok && k < a.ny) ? Xf[(size_t)f * a.nz + (slab + k) * rowst + zc] : 0.0f;
+        }
+      };
       if (SGS) {
         const Opd16<PREC> ap = load_a16<PREC>(a.ahi[0], a.alo[0], ao);
         const Opd16<PREC> am = load_a16<PREC>(a.ahi[1], a.alo[1], ao);
         const Opd16<PREC> cp = load_a16<PREC>(a.ahi[2], a.alo[2], ao);
         const Opd16<PREC> cm = load_a16<PREC>(a.ahi[3], a.alo[3], ao);
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-          const int zc = z0 + nt * 16 + col;
-          const bool zok = zc < a.nz;
-#pragma unroll
-          for (int f = 0; f < 9; ++f) {
-            float v[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const int k = kb + e;
-              v[e] = (zok && k < a.ny) ? Xf[f * a.in_stride + (slab + k) * a.nz + zc] : 0.0f;
-            }
-            const Opd16<PREC> bo = split8<PREC>(v);
-            switch (f) {
-              case 0:
-                acc[0][nt] = mma_b<PREC>(ap, bo, acc[0][nt]);
-                acc[3][nt] = mma_b<PREC>(cp, bo, acc[3][nt]);
-                acc[3][nt] = mma_b<PREC>(cp, bo, acc[3][nt]);
-                break;
-              case 1:
-                acc[1][nt] = mma_b<PREC>(am, bo, acc[1][nt]);
-                acc[4][nt] = mma_b<PREC>(cm, bo, acc[4][nt]);
-                break;
-              case 2:
-                acc[2][nt] = mma_b<PREC>(ap, bo, acc[2][nt]);
-                acc[5][nt] = mma_b<PREC>(cp, bo, acc[5][nt]);
-                break;
-              case 4:
-              case 7:
-                acc[f][nt] = mma_b<PREC>(am, bo, acc[f][nt]);
-                break;
-              default:
-                acc[f][nt] = mma_b<PREC>(ap, bo, acc[f][nt]);
-            }
+        for (int f = 0; f < 9; ++f) {
+          float v[8];
+          load8(f, v);
+          const Opd16<PREC> bo = split8<PREC>(v);
+          switch (f) {
+            case 0:
+              acc[0] = mma_b<PREC>(ap, bo, acc[0]);
+              acc[3] = mma_b<PREC>(cp, bo, acc[3]);
+              acc[3] = mma_b<PREC>(cp, bo, acc[3]);
+              break;
+            case 1:
+              acc[1] = mma_b<PREC>(am, bo, acc[1]);
+              acc[4] = mma_b<PREC>(cm, bo, acc[4]);
+              break;
+            case 2:
+              acc[2] = mma_b<PREC>(ap, bo, acc[2]);
+              acc[5] = mma_b<PREC>(cp, bo, acc[5]);
+              break;
+            case 4:
+            case 7:
+              acc[f] = mma_b<PREC>(am, bo, acc[f]);
+              break;
+            default:
+              acc[f] = mma_b<PREC>(ap, bo, acc[f]);
           }
         }
       } else {
         const Opd16<PREC> w = load_a16<PREC>(a.ahi[opsel], a.alo[opsel], ao);
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-          const int zc = z0 + nt * 16 + col;
-          const bool zok = zc < a.nz;
-          float v[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int k = kb + e;
-            v[e] = (zok && k < a.ny) ? Xf[(slab + k) * a.nz + zc] : 0.0f;
-          }
-          acc[0][nt] = mma_b<PREC>(w, split8<PREC>(v), acc[0][nt]);
-        }
+        float v[8];
+        load8(0, v);
+        acc[0] = mma_b<PREC>(w, split8<PREC>(v), acc[0]);
       }
     }
   }
 
   // ---- epilogue
   if (!SGS) {
+    if (!zok) return;
     float *dst = a.out + (size_t)field * a.out_stride;
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + 4 * grp + r, z = z0 + nt * 16 + col;
-        if (i < a.ny && z < a.nz) dst[(slab + i) * a.nz + z] = acc[0][nt][r];
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 4 * grp + r;
+      if (i < a.ny) dst[(slab + i) * a.nz + zc] = acc[0][r];
+    }
     return;
   }
+  __shared__ double red[kYWaves][9][kYBlockM];
   const size_t N = (size_t)a.nx * a.ny * a.nz;
   const float *Mp = a.prof32 + a.mpad;
   const float *Sp = a.prof32 + 2 * a.mpad;
-  double sums[9][4];
-#pragma unroll
-  for (int q = 0; q < 9; ++q)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) sums[q][r] = 0.0;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = i0 + 4 * grp + r;
-    const float mi = i < a.ny ? Mp[i] : 0.0f;
-    const float si = i < a.ny ? Sp[i] : 0.0f;
+    const bool ok = zok && i < a.ny;
+    const float mi = (live && i < a.ny) ? Mp[i] : 0.0f;
+    const float si = (live && i < a.ny) ? Sp[i] : 0.0f;
+    const float f0 = acc[0][r], f1 = acc[1][r], f2 = acc[2][r];
+    float o[9];
+    o[0] = f0 + mi;
+    o[1] = f1;
+    o[2] = f2;
+    o[3] = (acc[3][r] - f0 * f0) + si;
+    o[4] = acc[4][r] - f0 * f1;
+    o[5] = acc[5][r] - f0 * f2;
+    o[6] = acc[6][r] - f1 * f1;
+    o[7] = acc[7][r] - f1 * f2;
+    o[8] = acc[8][r] - f2 * f2;
+    if (ok) {
+      const size_t off = (slab + i) * a.nz + zc;
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      const int z = z0 + nt * 16 + col;
-      const bool ok = i < a.ny && z < a.nz;
-      const float f0 = acc[0][nt][r], f1 = acc[1][nt][r], f2 = acc[2][nt][r];
-      float o[9];
-      o[0] = f0 + mi;
-      o[1] = f1;
-      o[2] = f2;
-      o[3] = (acc[3][nt][r] - f0 * f0) + si;
-      o[4] = acc[4][nt][r] - f0 * f1;
-      o[5] = acc[5][nt][r] - f0 * f2;
-      o[6] = acc[6][nt][r] - f1 * f1;
-      o[7] = acc[7][nt][r] - f1 * f2;
-      o[8] = acc[8][nt][r] - f2 * f2;
-      if (ok) {
-        const size_t off = (slab + i) * a.nz + z;
+      for (int q = 0; q < 3; ++q) a.ubar[q * N + off] = o[q];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) a.ubar[q * N + off] = o[q];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) a.tau[q * N + off] = o[3 + q];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) sums[q][r] += (double)o[q];
-      }
+      for (int q = 0; q < 6; ++q) a.tau[q * N + off] = o[3 + q];
     }
-  }
-  if (a.part) {
+    if (a.part) {
+      // FP64 sum over the tile's 16 columns of row i
 #pragma unroll
-    for (int q = 0; q < 9; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double v = sums[q][r];
+      for (int q = 0; q < 9; ++q) {
+        double v = ok ? (double)o[q] : 0.0;
         v += __shfl_xor(v, 1);
         v += __shfl_xor(v, 2);
         v += __shfl_xor(v, 4);
         v += __shfl_xor(v, 8);
-        sums[q][r] = v;
+        if (col == 0) red[wave][q][4 * grp + r] = v;
       }
-    if (col == 0) {
-      const size_t P = (size_t)a.nx * a.n32;
-      const size_t p = (size_t)x * a.n32 + zt;
+    }
+  }
+  if (!a.part) return;
+  __syncthreads();
+  // the block's four tiles share (x, i-block): add them in a fixed order
+  if (item - wave < items && threadIdx.x < 9 * kYBlockM) {
+    const int q = threadIdx.x / kYBlockM, rr = threadIdx.x % kYBlockM;
+    const int i = i0 + rr;
+    if (i < a.ny) {
+      double v = red[0][q][rr];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + 4 * grp + r;
-        if (i < a.ny)
-#pragma unroll
-          for (int q = 0; q < 9; ++q) a.part[((size_t)q * a.ny + i) * P + p] = sums[q][r];
-      }
+      for (int w = 1; w < kYWaves; ++w) v += red[w][q][rr];
+      const size_t P = (size_t)a.nx * (nzt / kYWaves);
+      const size_t p = (size_t)x * (nzt / kYWaves) + zt / kYWaves;
+      a.part[((size_t)q * a.ny + i) * P + p] = v;
     }
   }
 }
@@ -328,7 +313,8 @@ __global__ void __launch_bounds__(kStatT) k_stats(const double *__restrict__ par
 
 template <bool SGS>
 hipError_t launch_y_t(const YArgs &a, int prec, hipStream_t s) {
-  const long items = (long)a.nx * (a.mpad / kYBlockM) * a.n32;
+  const int nzt = (a.n16 + kYWaves - 1) / kYWaves * kYWaves;
+  const long items = (long)a.nx * (a.mpad / kYBlockM) * nzt;
   const dim3 grid((unsigned)((items + kYWaves - 1) / kYWaves), SGS ? 1 : a.nfield);
   const dim3 block(64 * kYWaves);
   if (prec == 0)
