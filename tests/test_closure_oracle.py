@@ -1,0 +1,145 @@
+"""Pins of the FP64 closure reference: derivatives, network gradients, Adam,
+the counter-based sampler and the standardisation."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import closure_ref as C
+from paper_1902_02508_amd import synth
+
+
+def test_spectral_derivative_exact_on_modes():
+    n, L = 24, 3.0
+    x = np.arange(n) * L / n
+    for q in (0, 1, 5, 11):
+        k = 2 * np.pi * q / L
+        f = np.sin(k * x + 0.7)[:, None]
+        d = C.spectral_derivative(f, L, 0)
+        assert np.max(np.abs(d[:, 0] - k * np.cos(k * x + 0.7))) < 1e-12 * max(1, k)
+    # the Nyquist mode of an even length has no derivative
+    f = np.cos(np.pi * np.arange(n))[:, None]
+    assert np.max(np.abs(C.spectral_derivative(f, L, 0))) < 1e-12
+
+
+def test_dy_interior_exact_on_quadratics():
+    y = synth.ygrid(17, "tanh", 2.0)
+    f = 3.0 - 2.0 * y + 5.0 * y ** 2
+    for par in (1, -1):
+        D = C.dy_matrix(y, par)
+        assert np.max(np.abs((D @ f)[1:-1] - (-2.0 + 10.0 * y[1:-1]))) < 1e-12
+
+
+def test_dy_wall_rows_follow_the_extension():
+    # even about both walls: zero slope at the walls
+    for ny in (17, 33, 65):
+        y = synth.ygrid(ny, "cgl")
+        D = C.dy_matrix(y, 1)
+        f = np.cos(np.pi * (y + 1))
+        assert abs((D @ f)[0]) < 1e-14 and abs((D @ f)[-1]) < 1e-14
+    # odd about both walls: mirror-symmetric difference, second-order accurate
+    errs = []
+    for ny in (17, 33, 65):
+        y = synth.ygrid(ny, "uniform")
+        D = C.dy_matrix(y, -1)
+        f = np.sin(np.pi * (y + 1))
+        d = D @ f
+        errs.append(abs(d[0] - np.pi))
+        assert abs(d[0] - f[1] / (y[1] + 1)) < 1e-14
+    assert errs[1] / errs[2] > 3.5 and errs[0] / errs[1] > 3.5
+
+
+def test_features_of_an_analytic_field():
+    nx, ny, nz, lx, lz = 16, 21, 12, 2.0, 1.5
+    y = synth.ygrid(ny, "uniform")
+    x = np.arange(nx) * lx / nx
+    z = np.arange(nz) * lz / nz
+    X, Y, Z = np.meshgrid(x, y, z, indexing="ij")
+    kx, kz = 2 * np.pi * 2 / lx, 2 * np.pi / lz
+    ub = np.stack([np.sin(kx * X) * np.ones_like(Y), np.zeros_like(X), np.cos(kz * Z) * (1 + 0 * Y)])
+    f = C.features(ub, y, lx, lz)
+    assert np.max(np.abs(f[0] - kx * np.cos(kx * X))) < 1e-12
+    assert np.max(np.abs(f[8] + kz * np.sin(kz * Z))) < 1e-12
+    assert np.max(np.abs(f[[1, 2, 3, 4, 5, 6, 7]])) < 1e-12
+    assert np.allclose(f[9], 1 - np.abs(Y))
+
+
+def test_gelu_special_values():
+    assert C.gelu(0.0) == 0.0
+    assert abs(C.gelu_grad(0.0) - 0.5) < 1e-15
+    assert abs(C.gelu(10.0) - 10.0) < 1e-12 and abs(C.gelu(-10.0)) < 1e-12
+    x = np.linspace(-5, 5, 101)
+    h = 1e-6
+    fd = (C.gelu(x + h) - C.gelu(x - h)) / (2 * h)
+    assert np.max(np.abs(fd - C.gelu_grad(x))) < 1e-8
+
+
+def test_backprop_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    layers = (10, 8, 7, 6, 6)
+    th = C.init_params(3, layers) * 3
+    x = rng.standard_normal((5, 10))
+    t = rng.standard_normal((5, 6))
+    loss, g = C.loss_and_grad(th, x, t, layers)
+    h = 1e-6
+    idx = rng.choice(len(th), 60, replace=False)
+    for i in idx:
+        e = np.zeros_like(th)
+        e[i] = h
+        fd = (C.loss_and_grad(th + e, x, t, layers)[0] - C.loss_and_grad(th - e, x, t, layers)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_full_network_shape_and_count():
+    th = C.init_params(0)
+    assert len(th) == C.n_params() == 9414
+    y = C.forward(th, np.zeros((3, 10)))
+    assert y.shape == (3, 6)
+    lim = [1 / math.sqrt(a) for a in C.LAYERS[:-1]]
+    parts = C.unpack(th)
+    for l in range(4):
+        assert np.all(np.abs(parts[2 * l]) <= lim[l]) and np.all(np.abs(parts[2 * l + 1]) <= lim[l])
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    g = np.array([3.0, -0.02, 1e-3, -40.0])
+    th, m, v = C.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=1e-3)
+    assert np.allclose(th, -1e-3 * np.sign(g), rtol=1e-4)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_linear_network_reaches_least_squares():
+    rng = np.random.default_rng(4)
+    n, a, b = 512, 5, 3
+    X = rng.standard_normal((n, a))
+    Wt = rng.standard_normal((a, b))
+    T = X @ Wt + 0.3 + 0.05 * rng.standard_normal((n, b))
+    layers = (a, b)
+    th0 = C.init_params(1, layers)
+    th, m, v, losses = C.train(th0, X, T, steps=4000, batch=256, seed=9, lr=1e-2, layers=layers)
+    A = np.hstack([X, np.ones((n, 1))])
+    sol, *_ = np.linalg.lstsq(A, T, rcond=None)
+    W, bias = C.unpack(th, layers)
+    assert np.max(np.abs(W.T - sol[:a])) < 2e-2
+    assert np.max(np.abs(bias - sol[a])) < 2e-2
+
+
+def test_splitmix64_published_outputs():
+    # first outputs of the reference generator seeded with 1234567
+    ref = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+           4593380528125082431, 16408922859458223821]
+    assert [int(v) for v in C.splitmix64(1234567, np.arange(5, dtype=np.uint64))] == ref
+
+
+def test_sampler_indices_in_range_and_spread():
+    idx = C.sample_indices(7, 3, 65536, 1000)
+    assert idx.min() >= 0 and idx.max() < 1000
+    counts = np.bincount(idx.astype(np.int64), minlength=1000)
+    assert counts.min() > 30 and counts.max() < 110
+    assert not np.array_equal(idx, C.sample_indices(7, 4, 65536, 1000))
+
+
+def test_moments():
+    a = np.random.default_rng(0).standard_normal((2, 50, 4)) * np.array([1.0, 3.0])[:, None, None] + 2
+    mu, sd = C.moments(a)
+    assert np.allclose(mu, a.reshape(2, -1).mean(1)) and np.allclose(sd, a.reshape(2, -1).std(1))
