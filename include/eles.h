@@ -156,6 +156,88 @@ int32_t filter_profile_end(eles_filter f, double *ms /* [ELES_NPASS] */,
 
 void filter_destroy(eles_filter f);
 
+/* ======================================================================
+ * Learned closure of the exact stress.
+ *
+ * The paper proposes using the exact stress computed from DNS data to
+ * inform subgrid models, naming machine learning as one route (Sec. 2.1,
+ * last paragraph; Sec. 5). This closure is a perceptron 10 -> 64 -> 64 ->
+ * 64 -> 6 with GELU (x Phi(x)) hidden layers and a linear output. Its
+ * inputs at every grid point are the nine components d ubar_i / d x_k
+ * (i, k = 1..3, row-major) of the filtered velocity gradient and the wall
+ * distance 1 - |y|; its outputs are tau_11, tau_12, tau_13, tau_22, tau_23,
+ * tau_33. Inputs and outputs are standardised with training-set means and
+ * standard deviations. Weights and activations are BF16 on the matrix
+ * cores with FP32 accumulation; master weights and Adam moments are FP32.
+ * Parameters are packed W1 (64x10, row-major), b1, W2 (64x64), b2, W3, b3,
+ * W4 (6x64), b4: ELES_CLOSURE_NPARAM floats.
+ * ====================================================================== */
+#define ELES_CLOSURE_NPARAM 9414
+
+typedef struct eles_closure_s *eles_closure;
+
+typedef struct {
+  int32_t batch;      /* minibatch size, a multiple of 32                     */
+  int32_t steps;      /* Adam steps of this call                              */
+  uint64_t seed;      /* minibatch stream: draw n = step * batch + slot of
+                         SplitMix64(seed), index = ((r >> 32) * count) >> 32  */
+  float lr, beta1, beta2, eps;
+} eles_train_desc;
+
+/* Device bytes of a closure state. */
+size_t closure_state_bytes(void);
+
+/* Create a closure in the caller's state buffer. params: host
+ * [ELES_CLOSURE_NPARAM] initial weights; norms: host FP64 [32] = feature
+ * means [10], feature standard deviations [10], target means [6], target
+ * standard deviations [6]. Waits for its copies. Errors: EINVAL, ENOSPACE,
+ * ENUMERIC (non-finite values, non-positive deviations), EHIP. */
+int32_t closure_create(void *state, size_t state_bytes, const float *params, const double *norms,
+                       hipStream_t stream, eles_closure *out);
+
+/* Adam steps taken so far (-1 for a null handle). */
+int64_t closure_step(eles_closure c);
+
+/* Checkpoint blob: FP32 weights, Adam m and v, FP64 norms, int64 step. */
+size_t closure_blob_bytes(void);
+int32_t closure_get_params(eles_closure c, void *blob, size_t bytes);  /* waits for the device */
+int32_t closure_set_params(eles_closure c, const void *blob, size_t bytes);
+
+/* Features of a filtered velocity ubar (device [3][nx][ny][nz]) on the
+ * filter's grid: feat (device [10][nx][ny][nz]) = d ubar_i/dx (spectral,
+ * dense differentiation matrix), d/dy (three-point difference, wall rows
+ * through the mirror node with the eq. (7) parities), d/dz (spectral), in
+ * (i, k) row-major order, then 1 - |y|. Errors: EINVAL, EHIP. */
+int32_t closure_features(eles_filter f, const float *ubar, float *feat, hipStream_t stream);
+
+/* FP64 mean and standard deviation of every channel of data (device
+ * [nsnap][nchan][npts]) into out (device [2][nchan]). */
+size_t closure_moments_workspace_bytes(int32_t nchan);
+int32_t closure_moments(const float *data, int32_t nchan, int32_t nsnap, int64_t npts, double *out, void *ws,
+                        size_t ws_bytes, hipStream_t stream);
+
+/* Adam training on minibatches drawn from nsnap snapshots of features
+ * (device [nsnap][10][npts]) and exact stresses (device [nsnap][6][npts]);
+ * loss = mean squared error of the standardised outputs. loss_hist:
+ * device FP32 [steps] or NULL. A later call continues the same minibatch
+ * stream and Adam state. Errors: EINVAL, ENOSPACE, ENOTSUP, EHIP. */
+size_t closure_train_workspace_bytes(int32_t batch);
+int32_t closure_train(eles_closure c, const float *feat, const float *tau, int32_t nsnap, int64_t npts,
+                      const eles_train_desc *d, float *loss_hist, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Predicted stress from a filtered velocity: features, then the network.
+ * tau_pred: device [6][nx][ny][nz]; stats: device FP64 [6][ny] plane
+ * averages of tau_pred, or NULL. Errors: EINVAL, ENOSPACE, EHIP. */
+size_t closure_infer_workspace_bytes(eles_filter f);
+int32_t closure_infer(eles_closure c, eles_filter f, const float *ubar, float *tau_pred, double *stats, void *ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* The minibatch indices the trainer draws at `step` (device int64 [batch]). */
+int32_t closure_sample_indices(uint64_t seed, int64_t step, int32_t batch, uint64_t count, int64_t *out,
+                               hipStream_t stream);
+
+void closure_destroy(eles_closure c);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,7 @@ struct eles_filter_s {
   std::vector<double> y;
   int ygemm;
   eles::OpsView v;
+  eles::GradView gv;
   eles_state_layout lay;
   int zt, nzt, nxt, n16;
   size_t npts;
@@ -46,13 +47,17 @@ long half_width(int n, double length, double delta, double tau) {
 }
 
 struct Plan {
-  int mx, mz, mpad, kpad;
+  int mx, mz, mpad, kpad, mpx, kpx, mpz, kpz;
   double tau;
-  size_t off[16];
+  size_t off[32];   // one per state region (O_END <= 32)
   size_t bytes;
 };
 
-enum { O_Y, O_WP, O_WM, O_WX64, O_WZ64, O_SHIFT, O_WX32, O_WZ32, O_A32, O_AHI, O_ALO, O_RB, O_PROF, O_END };
+enum {
+  O_Y, O_WP, O_WM, O_WX64, O_WZ64, O_SHIFT, O_WX32, O_WZ32, O_A32, O_AHI, O_ALO, O_RB, O_PROF,
+  O_DX32, O_DXHI, O_DXLO, O_DXB, O_DZHI, O_DZLO, O_DY32, O_DYHI, O_DYLO, O_DYB, O_END
+};
+static_assert(O_END <= 32, "Plan::off holds 32 regions");
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -79,11 +84,18 @@ int32_t plan_filter(const eles_filter_desc *d, Plan *p) {
   p->mz = (int)mz;
   p->mpad = (d->ny + eles::kYBlockM - 1) / eles::kYBlockM * eles::kYBlockM;
   p->kpad = (d->ny + eles::kKAlign - 1) / eles::kKAlign * eles::kKAlign;
+  p->mpx = (d->nx + 15) / 16 * 16;
+  p->kpx = (d->nx + 31) / 32 * 32;
+  p->mpz = (d->nz + 15) / 16 * 16;
+  p->kpz = (d->nz + 31) / 32 * 32;
   const size_t ny = d->ny, mk = (size_t)p->mpad * p->kpad;
+  const size_t mkx = (size_t)p->mpx * p->kpx, mkz = (size_t)p->mpz * p->kpz;
   const size_t sz[O_END] = {
       ny * 8, ny * ny * 8, ny * ny * 8, (size_t)(2 * mx + 1) * 8, (size_t)(2 * mz + 1) * 8, 3 * ny * 8,
       (size_t)eles::tap_pad_len((int)mx) * 4, (size_t)eles::tap_pad_len((int)mz) * 4,
-      4 * mk * 4, 4 * mk * 2, 4 * mk * 2, (size_t)p->mpad * 2 * 4, (size_t)p->mpad * 3 * 4};
+      4 * mk * 4, 4 * mk * 2, 4 * mk * 2, (size_t)p->mpad * 2 * 4, (size_t)p->mpad * 3 * 4,
+      mkx * 4, mkx * 2, mkx * 2, (size_t)p->mpx * 2 * 4, mkz * 2, mkz * 2,
+      2 * mk * 4, 2 * mk * 2, 2 * mk * 2, (size_t)p->mpad * 2 * 4};
   size_t o = 0;
   for (int k = 0; k < O_END; ++k) {
     p->off[k] = o;
@@ -125,6 +137,35 @@ eles::OpsView make_view(const eles_filter_desc *d, const Plan &p, char *st) {
   v.rowband = (int *)(st + p.off[O_RB]);
   v.prof32 = (float *)(st + p.off[O_PROF]);
   return v;
+}
+
+eles::GradView make_grad_view(const eles_filter_desc *d, const Plan &p, char *st) {
+  eles::GradView g;
+  g.nx = d->nx;
+  g.ny = d->ny;
+  g.nz = d->nz;
+  g.lx = d->lx;
+  g.lz = d->lz;
+  g.mpx = p.mpx;
+  g.kpx = p.kpx;
+  g.mpz = p.mpz;
+  g.kpz = p.kpz;
+  g.mpy = p.mpad;
+  g.kpy = p.kpad;
+  g.dx32 = (float *)(st + p.off[O_DX32]);
+  g.dxhi = (uint16_t *)(st + p.off[O_DXHI]);
+  g.dxlo = (uint16_t *)(st + p.off[O_DXLO]);
+  g.dxband = (int *)(st + p.off[O_DXB]);
+  g.dzhi = (uint16_t *)(st + p.off[O_DZHI]);
+  g.dzlo = (uint16_t *)(st + p.off[O_DZLO]);
+  const size_t mk = (size_t)p.mpad * p.kpad;
+  for (int w = 0; w < 2; ++w) {
+    g.dy32[w] = (float *)(st + p.off[O_DY32]) + w * mk;
+    g.dyhi[w] = (uint16_t *)(st + p.off[O_DYHI]) + w * mk;
+    g.dylo[w] = (uint16_t *)(st + p.off[O_DYLO]) + w * mk;
+  }
+  g.dyband = (int *)(st + p.off[O_DYB]);
+  return g;
 }
 
 bool overlap(const void *a, size_t na, const void *b, size_t nb) {
@@ -238,6 +279,7 @@ int32_t filter_setup(const eles_filter_desc *desc, void *state, size_t state_byt
   f->d.y = f->y.data();
   f->ygemm = desc->ygemm;
   f->v = make_view(desc, p, (char *)state);
+  f->gv = make_grad_view(desc, p, (char *)state);
   f->npts = (size_t)desc->nx * desc->ny * desc->nz;
   f->zt = eles::xz_tile_z(desc->nz, p.mz);
   f->nzt = (desc->nz + f->zt - 1) / f->zt;
@@ -257,7 +299,8 @@ int32_t filter_setup(const eles_filter_desc *desc, void *state, size_t state_byt
   L.state_bytes = p.bytes;
   if (hipMemcpyAsync(f->v.y64, f->y.data(), desc->ny * sizeof(double), hipMemcpyHostToDevice, stream) !=
           hipSuccess ||
-      eles::launch_build_ops(f->v, stream) != hipSuccess) {
+      eles::launch_build_ops(f->v, stream) != hipSuccess ||
+      eles::launch_build_grad_ops(f->gv, f->v.y64, stream) != hipSuccess) {
     delete f;
     return ELES_EHIP;
   }
@@ -308,9 +351,13 @@ int32_t filter_fields(eles_filter f, const float *in, int32_t nfields, const int
     if (timed(f, 1, stream, [&] { return eles::launch_xz(xa, false, stream); }) != hipSuccess) return ELES_EHIP;
     eles::YArgs ya = y_args(f);
     ya.in = tmp;
-    ya.in_nf = nc;
+    ya.in_fs = f->d.nz;
+    ya.in_ks = (size_t)nc * f->d.nz;
+    ya.in_xs = (size_t)f->d.ny * ya.in_ks;
     ya.out = out + (size_t)g0 * n;
-    ya.out_stride = n;
+    ya.out_fs = n;
+    ya.out_ks = f->d.nz;
+    ya.out_xs = (size_t)f->d.ny * f->d.nz;
     ya.nfield = nc;
     ya.parity_mask = 0;
     for (int k = 0; k < nc; ++k)
@@ -350,7 +397,9 @@ int32_t sgs_stress(eles_filter f, const float *u, float *ubar, float *tau, doubl
   if (timed(f, 1, stream, [&] { return eles::launch_xz(xa, true, stream); }) != hipSuccess) return ELES_EHIP;
   eles::YArgs ya = y_args(f);
   ya.in = X;
-  ya.in_nf = 9;
+  ya.in_fs = f->d.nz;
+  ya.in_ks = (size_t)9 * f->d.nz;
+  ya.in_xs = (size_t)f->d.ny * ya.in_ks;
   ya.ubar = ubar;
   ya.tau = tau;
   ya.part = part;
@@ -411,5 +460,327 @@ void filter_destroy(eles_filter f) {
   release_events(f);
   delete f;
 }
+
+}  // extern "C"
+
+// ======================================================================
+// learned closure
+// ======================================================================
+
+struct eles_closure_s {
+  eles::ClosureView c;
+  double *norm64;     // device copy of the standardisation moments
+  long step;          // Adam steps taken so far
+};
+
+namespace {
+
+constexpr int kNorm = 2 * eles::kMlpIn + 2 * eles::kMlpOut;   // 32 moments
+constexpr int kNrm32 = 2 * eles::kMlpIn + 4 * eles::kMlpOut;  // derived scales and shifts
+
+enum { C_TH, C_M, C_V, C_W1, C_W2, C_W3, C_W4, C_W2T, C_W3T, C_W4T, C_N64, C_N32, C_END };
+
+size_t closure_layout(size_t *off) {
+  const int P = eles::kMlpNParam, H = eles::kMlpHidden, K1 = eles::kMlpInPad;
+  const size_t sz[C_END] = {(size_t)P * 4, (size_t)P * 4, (size_t)P * 4, (size_t)H * K1 * 2, (size_t)H * H * 2,
+                            (size_t)H * H * 2, (size_t)16 * H * 2, (size_t)H * H * 2, (size_t)H * H * 2,
+                            (size_t)H * K1 * 2, (size_t)kNorm * 8, (size_t)kNrm32 * 4};
+  size_t o = 0;
+  for (int k = 0; k < C_END; ++k) {
+    if (off) off[k] = o;
+    o += up256(sz[k]);
+  }
+  return o;
+}
+
+bool valid_norms(const double *n) {
+  for (int k = 0; k < kNorm; ++k)
+    if (!std::isfinite(n[k])) return false;
+  for (int k = 0; k < eles::kMlpIn; ++k)
+    if (!(n[eles::kMlpIn + k] > 0.0)) return false;
+  for (int k = 0; k < eles::kMlpOut; ++k)
+    if (!(n[2 * eles::kMlpIn + eles::kMlpOut + k] > 0.0)) return false;
+  return true;
+}
+
+// Host-side FP32 scale/shift pairs of the standardisation.
+void derive_nrm32(const double *n, float *o) {
+  const int I = eles::kMlpIn, O = eles::kMlpOut;
+  for (int k = 0; k < I; ++k) {
+    o[k] = (float)(1.0 / n[I + k]);
+    o[I + k] = (float)(-n[k] / n[I + k]);
+  }
+  for (int k = 0; k < O; ++k) {
+    const double mu = n[2 * I + k], sd = n[2 * I + O + k];
+    o[2 * I + k] = (float)(1.0 / sd);
+    o[2 * I + O + k] = (float)(-mu / sd);
+    o[2 * I + 2 * O + k] = (float)sd;
+    o[2 * I + 3 * O + k] = (float)mu;
+  }
+}
+
+size_t train_ws(int batch, eles::TrainWs *w, char *base) {
+  const size_t B = batch, H = eles::kMlpHidden, K1 = eles::kMlpInPad;
+  const int nch = (batch + eles::kMlpChunk - 1) / eles::kMlpChunk;
+  const int mrows[4] = {64, 64, 64, 16}, ncols[4] = {eles::kMlpIn, 64, 64, 64};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char *p = base ? base + o : nullptr;
+    o += up256(bytes);
+    return p;
+  };
+  eles::TrainWs t{};
+  t.x0 = (uint16_t *)take(B * K1 * 2);
+  t.x0t = (uint16_t *)take(eles::kMlpIn * B * 2);
+  t.tb = (float *)take(B * 8 * 4);
+  for (int l = 0; l < 3; ++l) {
+    t.h[l] = (uint16_t *)take(B * H * 2);
+    t.ht[l] = (uint16_t *)take(H * B * 2);
+    t.g[l] = (uint16_t *)take(B * H * 2);
+    t.dz[l] = (uint16_t *)take(B * H * 2);
+    t.dzt[l] = (uint16_t *)take(H * B * 2);
+  }
+  t.dy = (uint16_t *)take(B * K1 * 2);
+  t.dyt = (uint16_t *)take(16 * B * 2);
+  for (int l = 0; l < 4; ++l) {
+    t.pw[l] = (float *)take((size_t)nch * mrows[l] * ncols[l] * 4);
+    t.pb[l] = (float *)take((size_t)nch * mrows[l] * 4);
+  }
+  t.lossp = (double *)take(B / 16 * 8);
+  if (w) *w = t;
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t closure_state_bytes(void) { return closure_layout(nullptr); }
+
+int32_t closure_create(void *state, size_t state_bytes, const float *params, const double *norms,
+                       hipStream_t stream, eles_closure *out) {
+  if (!out) return ELES_EINVAL;
+  *out = nullptr;
+  if (!state || !params || !norms || !aligned16(state)) return ELES_EINVAL;
+  size_t off[C_END];
+  const size_t need = closure_layout(off);
+  if (state_bytes < need) return ELES_ENOSPACE;
+  for (int k = 0; k < eles::kMlpNParam; ++k)
+    if (!std::isfinite(params[k])) return ELES_ENUMERIC;
+  if (!valid_norms(norms)) return ELES_ENUMERIC;
+  eles_closure_s *h = new (std::nothrow) eles_closure_s;
+  if (!h) return ELES_EINVAL;
+  char *st = (char *)state;
+  eles::ClosureView &c = h->c;
+  c.theta = (float *)(st + off[C_TH]);
+  c.m = (float *)(st + off[C_M]);
+  c.v = (float *)(st + off[C_V]);
+  c.w1 = (uint16_t *)(st + off[C_W1]);
+  c.w2 = (uint16_t *)(st + off[C_W2]);
+  c.w3 = (uint16_t *)(st + off[C_W3]);
+  c.w4 = (uint16_t *)(st + off[C_W4]);
+  c.w2t = (uint16_t *)(st + off[C_W2T]);
+  c.w3t = (uint16_t *)(st + off[C_W3T]);
+  c.w4t = (uint16_t *)(st + off[C_W4T]);
+  h->norm64 = (double *)(st + off[C_N64]);
+  float *n32 = (float *)(st + off[C_N32]);
+  const int I = eles::kMlpIn, O = eles::kMlpOut;
+  c.fsc = n32;
+  c.fsh = n32 + I;
+  c.tsc = n32 + 2 * I;
+  c.tsh = n32 + 2 * I + O;
+  c.isc = n32 + 2 * I + 2 * O;
+  c.ish = n32 + 2 * I + 3 * O;
+  h->step = 0;
+  float nrm[kNrm32];
+  derive_nrm32(norms, nrm);
+  const size_t pbytes = (size_t)eles::kMlpNParam * 4;
+  bool ok = hipMemsetAsync(st, 0, need, stream) == hipSuccess &&
+            hipMemcpyAsync(c.theta, params, pbytes, hipMemcpyHostToDevice, stream) == hipSuccess &&
+            hipMemcpyAsync(h->norm64, norms, kNorm * 8, hipMemcpyHostToDevice, stream) == hipSuccess &&
+            hipMemcpyAsync(n32, nrm, sizeof(nrm), hipMemcpyHostToDevice, stream) == hipSuccess &&
+            eles::launch_shadows(c, stream) == hipSuccess && hipStreamSynchronize(stream) == hipSuccess;
+  if (!ok) {
+    delete h;
+    return ELES_EHIP;
+  }
+  *out = h;
+  return ELES_OK;
+}
+
+int64_t closure_step(eles_closure c) { return c ? c->step : -1; }
+
+size_t closure_blob_bytes(void) { return (size_t)3 * eles::kMlpNParam * 4 + kNorm * 8 + 8; }
+
+int32_t closure_get_params(eles_closure c, void *blob, size_t bytes) {
+  if (!c || !blob || bytes < closure_blob_bytes()) return ELES_EINVAL;
+  const size_t pb = (size_t)eles::kMlpNParam * 4;
+  char *b = (char *)blob;
+  if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(b, c->c.theta, pb, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(b + pb, c->c.m, pb, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(b + 2 * pb, c->c.v, pb, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(b + 3 * pb, c->norm64, kNorm * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return ELES_EHIP;
+  int64_t st = c->step;
+  std::memcpy(b + 3 * pb + kNorm * 8, &st, 8);
+  return ELES_OK;
+}
+
+int32_t closure_set_params(eles_closure c, const void *blob, size_t bytes) {
+  if (!c || !blob || bytes < closure_blob_bytes()) return ELES_EINVAL;
+  const size_t pb = (size_t)eles::kMlpNParam * 4;
+  const char *b = (const char *)blob;
+  const float *f = (const float *)b;
+  for (int k = 0; k < 3 * eles::kMlpNParam; ++k)
+    if (!std::isfinite(f[k])) return ELES_ENUMERIC;
+  const double *n = (const double *)(b + 3 * pb);
+  if (!valid_norms(n)) return ELES_ENUMERIC;
+  int64_t st;
+  std::memcpy(&st, b + 3 * pb + kNorm * 8, 8);
+  if (st < 0) return ELES_EINVAL;
+  float nrm[kNrm32];
+  derive_nrm32(n, nrm);
+  if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(c->c.theta, b, pb, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->c.m, b + pb, pb, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->c.v, b + 2 * pb, pb, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->norm64, n, kNorm * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy((void *)c->c.fsc, nrm, sizeof(nrm), hipMemcpyHostToDevice) != hipSuccess ||
+      eles::launch_shadows(c->c, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+    return ELES_EHIP;
+  c->step = st;
+  return ELES_OK;
+}
+
+int32_t closure_features(eles_filter f, const float *ubar, float *feat, hipStream_t stream) {
+  if (!f || !ubar || !feat || !aligned16(ubar) || !aligned16(feat)) return ELES_EINVAL;
+  const size_t n = f->npts;
+  if (overlap(ubar, 3 * n * 4, feat, 10 * n * 4)) return ELES_EINVAL;
+  const int nx = f->d.nx, ny = f->d.ny, nz = f->d.nz;
+  const eles::GradView &g = f->gv;
+  // d/dx: the dense spectral operator along x, the field seen as one
+  // [nx] x [ny nz] slab
+  eles::YArgs ya = y_args(f);
+  for (int w = 0; w < 4; ++w) {
+    ya.a32[w] = g.dx32;
+    ya.ahi[w] = g.dxhi;
+    ya.alo[w] = g.dxlo;
+  }
+  ya.rowband = g.dxband;
+  ya.mpad = g.mpx;
+  ya.kpad = g.kpx;
+  ya.nx = 1;
+  ya.ny = nx;
+  ya.nz = ny * nz;
+  ya.n16 = (ny * nz + eles::kYTileN - 1) / eles::kYTileN;
+  ya.nfield = 3;
+  ya.parity_mask = 0;
+  ya.in = ubar;
+  ya.in_fs = n;
+  ya.in_xs = 0;
+  ya.in_ks = (size_t)ny * nz;
+  ya.out = feat;
+  ya.out_fs = 3 * n;
+  ya.out_xs = 0;
+  ya.out_ks = (size_t)ny * nz;
+  if (eles::launch_y(ya, false, ELES_YGEMM_BF16X3, stream) != hipSuccess) return ELES_EHIP;
+  // d/dy: three-point difference with the parities of (u1, u2, u3)
+  eles::YArgs yb = y_args(f);
+  yb.a32[0] = g.dy32[0];
+  yb.a32[1] = g.dy32[1];
+  yb.ahi[0] = g.dyhi[0];
+  yb.ahi[1] = g.dyhi[1];
+  yb.alo[0] = g.dylo[0];
+  yb.alo[1] = g.dylo[1];
+  yb.rowband = g.dyband;
+  yb.nfield = 3;
+  yb.parity_mask = 0x2;
+  yb.in = ubar;
+  yb.in_fs = n;
+  yb.in_xs = (size_t)ny * nz;
+  yb.in_ks = nz;
+  yb.out = feat + n;
+  yb.out_fs = 3 * n;
+  yb.out_xs = (size_t)ny * nz;
+  yb.out_ks = nz;
+  if (eles::launch_y(yb, false, ELES_YGEMM_FP32, stream) != hipSuccess) return ELES_EHIP;
+  // d/dz: rows times the transposed spectral operator
+  if (eles::launch_dz(g, ubar, feat + 2 * n, (long)(3 * n), stream) != hipSuccess) return ELES_EHIP;
+  if (eles::launch_walldist(f->v.y64, nx, ny, nz, feat + 9 * n, stream) != hipSuccess) return ELES_EHIP;
+  return ELES_OK;
+}
+
+size_t closure_moments_workspace_bytes(int32_t nchan) {
+  return nchan < 1 ? 0 : up256((size_t)nchan * 1024 * 8);
+}
+
+int32_t closure_moments(const float *data, int32_t nchan, int32_t nsnap, int64_t npts, double *out, void *ws,
+                        size_t ws_bytes, hipStream_t stream) {
+  if (!data || !out || !ws || nchan < 1 || nchan > 64 || nsnap < 1 || npts < 1) return ELES_EINVAL;
+  if (ws_bytes < closure_moments_workspace_bytes(nchan)) return ELES_ENOSPACE;
+  return eles::launch_moments(data, nchan, nsnap, (long)npts, (double *)ws, 1024, out, stream) == hipSuccess
+             ? ELES_OK
+             : ELES_EHIP;
+}
+
+size_t closure_train_workspace_bytes(int32_t batch) {
+  if (batch < 32 || batch % 32) return 0;
+  return train_ws(batch, nullptr, nullptr);
+}
+
+int32_t closure_train(eles_closure c, const float *feat, const float *tau, int32_t nsnap, int64_t npts,
+                      const eles_train_desc *td, float *loss_hist, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!c || !feat || !tau || !td || !ws || nsnap < 1 || npts < 1) return ELES_EINVAL;
+  if (td->batch < 32 || td->batch % 32 || td->steps < 0) return ELES_EINVAL;
+  if (!(td->lr > 0.0f) || !(td->beta1 >= 0.0f && td->beta1 < 1.0f) || !(td->beta2 >= 0.0f && td->beta2 < 1.0f) ||
+      !(td->eps > 0.0f))
+    return ELES_EINVAL;
+  if ((double)nsnap * npts > 4294967295.0) return ELES_ENOTSUP;
+  if (ws_bytes < closure_train_workspace_bytes(td->batch)) return ELES_ENOSPACE;
+  eles::TrainWs w;
+  train_ws(td->batch, &w, (char *)ws);
+  if (hipMemsetAsync(w.dy, 0, (size_t)td->batch * eles::kMlpInPad * 2, stream) != hipSuccess) return ELES_EHIP;
+  eles::TrainData d{feat, tau, nsnap, (long)npts};
+  for (int s = 0; s < td->steps; ++s) {
+    const long t = c->step + s + 1;
+    eles::AdamArgs a{};
+    a.lr = td->lr;
+    a.b1 = td->beta1;
+    a.b2 = td->beta2;
+    a.eps = td->eps;
+    a.bc1 = (float)(1.0 / (1.0 - std::pow((double)td->beta1, (double)t)));
+    a.bc2 = (float)(1.0 / (1.0 - std::pow((double)td->beta2, (double)t)));
+    a.loss_out = loss_hist ? loss_hist + s : nullptr;
+    if (eles::launch_train_step(c->c, d, w, td->seed, t - 1, td->batch, a, stream) != hipSuccess) return ELES_EHIP;
+  }
+  c->step += td->steps;
+  return ELES_OK;
+}
+
+size_t closure_infer_workspace_bytes(eles_filter f) { return f ? up256(10 * f->npts * 4) : 0; }
+
+int32_t closure_infer(eles_closure c, eles_filter f, const float *ubar, float *tau_pred, double *stats, void *ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  if (!c || !f || !ubar || !tau_pred || !ws || !aligned16(tau_pred) || !aligned16(ws)) return ELES_EINVAL;
+  if (ws_bytes < closure_infer_workspace_bytes(f)) return ELES_ENOSPACE;
+  const size_t n = f->npts;
+  if (overlap(ubar, 3 * n * 4, tau_pred, 6 * n * 4) || overlap(ws, ws_bytes, tau_pred, 6 * n * 4) ||
+      overlap(ws, ws_bytes, ubar, 3 * n * 4))
+    return ELES_EINVAL;
+  float *feat = (float *)ws;
+  int32_t st = closure_features(f, ubar, feat, stream);
+  if (st != ELES_OK) return st;
+  if (eles::launch_infer(c->c, feat, (long)n, tau_pred, stream) != hipSuccess) return ELES_EHIP;
+  if (stats && eles::launch_plane_mean(tau_pred, 6, f->d.nx, f->d.ny, f->d.nz, stats, stream) != hipSuccess)
+    return ELES_EHIP;
+  return ELES_OK;
+}
+
+int32_t closure_sample_indices(uint64_t seed, int64_t step, int32_t batch, uint64_t count, int64_t *out,
+                               hipStream_t stream) {
+  if (!out || batch < 1 || step < 0 || count < 1 || count > 4294967296ull) return ELES_EINVAL;
+  return eles::launch_sample(seed, (long)step, batch, count, out, stream) == hipSuccess ? ELES_OK : ELES_EHIP;
+}
+
+void closure_destroy(eles_closure c) { delete c; }
 
 }  // extern "C"

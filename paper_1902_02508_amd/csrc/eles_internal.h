@@ -62,11 +62,13 @@ int xz_tile_z(int nz, int mz);
 
 // y pass, k_y.hip.
 struct YArgs {
-  const float *in;        // x/z-filtered fields, [nx][ny][in_nf][nz]
-  int in_nf;
-  float *ubar, *tau;      // sgs outputs
-  float *out;             // plain outputs
-  size_t out_stride;
+  // element (x, k, z) of input field f sits at in[f*in_fs + x*in_xs + k*in_ks + z];
+  // the stress mode reads the row-interleaved x/z-pass output
+  const float *in;
+  size_t in_fs, in_xs, in_ks;
+  float *ubar, *tau;      // sgs outputs, planar [3][nx][ny][nz] / [6][...]
+  float *out;             // plain outputs, element (x, i, z) of field f at
+  size_t out_fs, out_xs, out_ks;   // out[f*out_fs + x*out_xs + i*out_ks + z]
   double *part;           // sgs plane partials [9][ny][y_parts()] or null
   const float *a32[4];
   const uint16_t *ahi[4], *alo[4];
@@ -80,5 +82,67 @@ hipError_t launch_y(const YArgs &a, bool sgs, int prec, hipStream_t s);
 inline int y_parts(int nx, int n16) { return nx * ((n16 + kYWaves - 1) / kYWaves); }
 hipError_t launch_stats(const double *part, double *stats, int ny, int nparts,
                         double inv_count, hipStream_t s);
+
+// ---- closure features: gradient operators of the grid (filter state)
+struct GradView {
+  int nx, ny, nz, mpx, kpx, mpz, kpz, mpy, kpy;
+  double lx, lz;
+  float *dx32;                 // spectral x derivative, padded [mpx][kpx]
+  uint16_t *dxhi, *dxlo;
+  int *dxband;                 // [mpx][2]
+  uint16_t *dzhi, *dzlo;       // spectral z derivative, padded [mpz][kpz]
+  float *dy32[2];              // y derivative of even / odd fields [mpy][kpy]
+  uint16_t *dyhi[2], *dylo[2];
+  int *dyband;                 // [mpy][2]
+};
+hipError_t launch_build_grad_ops(const GradView &v, const double *y64, hipStream_t s);
+hipError_t launch_dz(const GradView &v, const float *ubar, float *out, long out_fstride, hipStream_t s);
+hipError_t launch_walldist(const double *y64, int nx, int ny, int nz, float *out, hipStream_t s);
+
+// ---- the perceptron
+constexpr int kMlpIn = 10, kMlpHidden = 64, kMlpOut = 6, kMlpInPad = 32;
+constexpr int kMlpNParam = 10 * 64 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 * 6 + 6;
+constexpr int kMlpOffB1 = 640, kMlpOffB2 = 640 + 64 + 4096, kMlpOffB3 = kMlpOffB2 + 64 + 4096,
+              kMlpOffB4 = kMlpOffB3 + 64 + 384;
+constexpr int kMlpChunk = 512;   // batch rows per split-K chunk of a weight gradient
+
+struct ClosureView {
+  float *theta, *m, *v;                         // FP32 master weights and Adam moments
+  uint16_t *w1, *w2, *w3, *w4, *w2t, *w3t, *w4t;  // padded BF16 shadows
+  const float *fsc, *fsh;                       // standardised feature = f * fsc + fsh
+  const float *tsc, *tsh;                       // standardised target  = t * tsc + tsh
+  const float *isc, *ish;                       // target = y * isc + ish
+};
+struct TrainData {
+  const float *feat, *tau;   // [nsnap][10][npts], [nsnap][6][npts]
+  int nsnap;
+  long npts;
+};
+struct TrainWs {
+  uint16_t *x0, *x0t;
+  float *tb;
+  uint16_t *h[3], *ht[3], *g[3], *dy, *dyt, *dz[3], *dzt[3];
+  float *pw[4], *pb[4];
+  double *lossp;
+};
+struct AdamArgs {
+  float lr, b1, b2, eps, bc1, bc2;
+  float *loss_out;
+  const double *lossp;
+  int nloss;
+  long batch;
+  int nchunks;
+  const float *pw[4];
+  const float *pb[4];
+  int mrows[4], ncols[4];
+};
+hipError_t launch_sample(uint64_t seed, long step, int batch, uint64_t count, int64_t *out, hipStream_t s);
+hipError_t launch_shadows(const ClosureView &c, hipStream_t s);
+hipError_t launch_infer(const ClosureView &c, const float *feat, long npts, float *out, hipStream_t s);
+hipError_t launch_moments(const float *data, int nchan, int nsnap, long npts, double *part, int nchunks,
+                          double *out, hipStream_t s);
+hipError_t launch_plane_mean(const float *f, int nq, int nx, int ny, int nz, double *out, hipStream_t s);
+hipError_t launch_train_step(const ClosureView &c, const TrainData &d, const TrainWs &w, uint64_t seed, long step,
+                             int batch, AdamArgs adam, hipStream_t s);
 
 }  // namespace eles

@@ -126,8 +126,7 @@ k_y(YArgs a, const float *__restrict__ X, const int *__restrict__ rowband) {
   for (int f = 0; f < NA; ++f) acc[f] = f4{0.f, 0.f, 0.f, 0.f};
 
   const size_t slab = (size_t)x * a.ny;
-  const size_t rowst = (size_t)a.in_nf * a.nz;    // one (x, y) row of all fields
-  const float *Xf = X + (SGS ? 0 : (size_t)field * a.nz);
+  const float *Xf = X + (size_t)field * a.in_fs + (size_t)x * a.in_xs;
 
   if (PREC == 0) {
     // B fragments arrive two K steps ahead of the matrix instructions
@@ -136,10 +135,10 @@ k_y(YArgs a, const float *__restrict__ X, const int *__restrict__ rowband) {
     auto load_b = [&](int k0, float (&dst)[NA]) {
       const int kk = k0 + grp;
       const bool ok = zok && kk < a.ny && k0 < khi;
-      const size_t off = (slab + (ok ? kk : 0)) * rowst + (ok ? zc : 0);
+      const size_t off = (size_t)(ok ? kk : 0) * a.in_ks + (ok ? zc : 0);
 #pragma unroll
       for (int f = 0; f < NA; ++f) {
-        const float t = Xf[(size_t)f * a.nz + off];
+        const float t = Xf[(size_t)f * a.in_fs + off];
         dst[f] = ok ? t : 0.0f;
       }
     };
@@ -181,7 +180,7 @@ k_y(YArgs a, const float *__restrict__ X, const int *__restrict__ rowband) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int k = kb + e;
-          v[e] = (zok && k < a.ny) ? Xf[(size_t)f * a.nz + (slab + k) * rowst + zc] : 0.0f;
+          v[e] = (zok && k < a.ny) ? Xf[(size_t)f * a.in_fs + (size_t)k * a.in_ks + zc] : 0.0f;
         }
       };
       if (SGS) {
@@ -228,11 +227,11 @@ k_y(YArgs a, const float *__restrict__ X, const int *__restrict__ rowband) {
   // ---- epilogue
   if (!SGS) {
     if (!zok) return;
-    float *dst = a.out + (size_t)field * a.out_stride;
+    float *dst = a.out + (size_t)field * a.out_fs + (size_t)x * a.out_xs;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = i0 + 4 * grp + r;
-      if (i < a.ny) dst[(slab + i) * a.nz + zc] = acc[0][r];
+      if (i < a.ny) dst[(size_t)i * a.out_ks + zc] = acc[0][r];
     }
     return;
   }

@@ -64,6 +64,21 @@ _SIG = {
     "filter_profile_begin": (_I, [_P, _I]),
     "filter_profile_end": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)]),
     "filter_destroy": (None, [_P]),
+    "closure_state_bytes": (_S, []),
+    "closure_create": (_I, [_P, _S, _P, _P, _P, ctypes.POINTER(_P)]),
+    "closure_step": (ctypes.c_int64, [_P]),
+    "closure_blob_bytes": (_S, []),
+    "closure_get_params": (_I, [_P, _P, _S]),
+    "closure_set_params": (_I, [_P, _P, _S]),
+    "closure_features": (_I, [_P, _P, _P, _P]),
+    "closure_moments_workspace_bytes": (_S, [_I]),
+    "closure_moments": (_I, [_P, _I, _I, ctypes.c_int64, _P, _P, _S, _P]),
+    "closure_train_workspace_bytes": (_S, [_I]),
+    "closure_train": (_I, [_P, _P, _P, _I, ctypes.c_int64, _P, _P, _P, _S, _P]),
+    "closure_infer_workspace_bytes": (_S, [_P]),
+    "closure_infer": (_I, [_P, _P, _P, _P, _P, _P, _S, _P]),
+    "closure_sample_indices": (_I, [ctypes.c_uint64, ctypes.c_int64, _I, ctypes.c_uint64, _P, _P]),
+    "closure_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _SIG.items():
     _fn = getattr(lib, _name)
@@ -71,6 +86,15 @@ for _name, (_res, _args) in _SIG.items():
     _fn.argtypes = _args
 
 EXPORTS = tuple(_SIG)
+
+
+NPARAM = 9414
+
+
+class TrainDesc(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
 
 
 class ElesError(RuntimeError):
@@ -262,3 +286,173 @@ class Filter:
             "shift": f64(L.off_shift, 3 * ny).reshape(3, ny),
             "mx": L.mx, "mz": L.mz,
         }
+
+
+# ---- the learned closure ----------------------------------------------------
+
+def closure_state_bytes() -> int:
+    return lib.closure_state_bytes()
+
+
+def closure_create(state_ptr, state_bytes, params_host, norms_host, stream):
+    h = _P()
+    _check(lib.closure_create(state_ptr, state_bytes, params_host, norms_host, stream, ctypes.byref(h)),
+           "closure_create")
+    return h
+
+
+def closure_step(h) -> int:
+    return lib.closure_step(h)
+
+
+def closure_blob_bytes() -> int:
+    return lib.closure_blob_bytes()
+
+
+def closure_get_params(h) -> bytes:
+    n = lib.closure_blob_bytes()
+    buf = ctypes.create_string_buffer(n)
+    _check(lib.closure_get_params(h, buf, n), "closure_get_params")
+    return buf.raw
+
+
+def closure_set_params(h, blob: bytes):
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(lib.closure_set_params(h, buf, len(blob)), "closure_set_params")
+
+
+def closure_features(fh, ubar_ptr, feat_ptr, stream):
+    _check(lib.closure_features(fh, ubar_ptr, feat_ptr, stream), "closure_features")
+
+
+def closure_moments_workspace_bytes(nchan: int) -> int:
+    return lib.closure_moments_workspace_bytes(nchan)
+
+
+def closure_moments(data_ptr, nchan, nsnap, npts, out_ptr, ws_ptr, ws_bytes, stream):
+    _check(lib.closure_moments(data_ptr, nchan, nsnap, npts, out_ptr, ws_ptr, ws_bytes, stream), "closure_moments")
+
+
+def closure_train_workspace_bytes(batch: int) -> int:
+    return lib.closure_train_workspace_bytes(batch)
+
+
+def closure_train(h, feat_ptr, tau_ptr, nsnap, npts, desc, loss_ptr, ws_ptr, ws_bytes, stream):
+    _check(lib.closure_train(h, feat_ptr, tau_ptr, nsnap, npts, ctypes.byref(desc), loss_ptr, ws_ptr, ws_bytes,
+                             stream), "closure_train")
+
+
+def closure_infer_workspace_bytes(fh) -> int:
+    return lib.closure_infer_workspace_bytes(fh)
+
+
+def closure_infer(h, fh, ubar_ptr, tau_ptr, stats_ptr, ws_ptr, ws_bytes, stream):
+    _check(lib.closure_infer(h, fh, ubar_ptr, tau_ptr, stats_ptr, ws_ptr, ws_bytes, stream), "closure_infer")
+
+
+def closure_sample_indices(seed, step, batch, count, out_ptr, stream):
+    _check(lib.closure_sample_indices(seed, step, batch, count, out_ptr, stream), "closure_sample_indices")
+
+
+def closure_destroy(h):
+    lib.closure_destroy(h)
+
+
+def features(f: "Filter", ubar: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """closure_features for a Filter's grid: [10][nx][ny][nz] FP32."""
+    f._field_check(ubar, 3)
+    if out is None:
+        out = torch.empty((10,) + f.shape, dtype=torch.float32, device=f.device)
+    f._field_check(out, 10)
+    closure_features(f.h, _ptr(ubar), _ptr(out), _stream())
+    return out
+
+
+def moments(data: torch.Tensor) -> torch.Tensor:
+    """FP64 [2][C] mean and standard deviation per channel of [S][C][...] data."""
+    if data.dtype != torch.float32 or not data.is_contiguous():
+        raise ValueError("data must be contiguous float32")
+    S, C = data.shape[0], data.shape[1]
+    npts = data[0, 0].numel()
+    out = torch.empty((2, C), dtype=torch.float64, device=data.device)
+    ws = torch.empty(closure_moments_workspace_bytes(C), dtype=torch.uint8, device=data.device)
+    closure_moments(_ptr(data), C, S, npts, _ptr(out), _ptr(ws), ws.numel(), _stream())
+    return out
+
+
+class Closure:
+    """A closure handle; state, workspace and norms live on the current device."""
+
+    def __init__(self, params: np.ndarray, norms: np.ndarray, device="cuda"):
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        n = np.ascontiguousarray(norms, dtype=np.float64)
+        if p.size != NPARAM or n.size != 32:
+            raise ValueError("params must hold 9414 values and norms 32")
+        self.state = torch.empty(closure_state_bytes(), dtype=torch.uint8, device=dev)
+        self.h = closure_create(_ptr(self.state), self.state.numel(), p.ctypes.data_as(_P),
+                                n.ctypes.data_as(_P), _stream())
+        self._ws = torch.empty(0, dtype=torch.uint8, device=dev)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            closure_destroy(h)
+            self.h = None
+
+    def _workspace(self, nbytes):
+        if self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    @property
+    def step(self) -> int:
+        return closure_step(self.h)
+
+    def get_params(self) -> bytes:
+        return closure_get_params(self.h)
+
+    def set_params(self, blob: bytes):
+        closure_set_params(self.h, blob)
+
+    def theta(self) -> np.ndarray:
+        return np.frombuffer(self.get_params(), dtype=np.float32, count=NPARAM).copy()
+
+    def train(self, feat: torch.Tensor, tau: torch.Tensor, steps: int, batch: int = 65536, seed: int = 1,
+              lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+              loss_hist: Optional[torch.Tensor] = None):
+        """feat [S][10][...], tau [S][6][...] on the device."""
+        S = feat.shape[0]
+        npts = feat[0, 0].numel()
+        if tuple(tau.shape[:2]) != (S, 6) or feat.shape[1] != 10 or tau[0, 0].numel() != npts:
+            raise ValueError("feat must be [S][10][...] and tau [S][6][...] over the same points")
+        d = TrainDesc(batch, steps, seed, lr, beta1, beta2, eps)
+        nb = closure_train_workspace_bytes(batch)
+        if nb == 0:
+            raise ValueError("batch must be a positive multiple of 32")
+        ws = self._workspace(nb)
+        if loss_hist is None and steps > 0:
+            loss_hist = torch.empty(steps, dtype=torch.float32, device=self.device)
+        closure_train(self.h, _ptr(feat), _ptr(tau), S, npts, d, _ptr(loss_hist) if steps > 0 else None,
+                      _ptr(ws), ws.numel(), _stream())
+        return loss_hist
+
+    def infer(self, f: "Filter", ubar: torch.Tensor, tau: Optional[torch.Tensor] = None, stats=True):
+        f._field_check(ubar, 3)
+        if tau is None:
+            tau = torch.empty((6,) + f.shape, dtype=torch.float32, device=f.device)
+        st = torch.empty((6, f.shape[1]), dtype=torch.float64, device=f.device) if stats is True else stats
+        nb = closure_infer_workspace_bytes(f.h)
+        ws = self._workspace(nb)
+        closure_infer(self.h, f.h, _ptr(ubar), _ptr(tau), _ptr(st) if st is not None else None,
+                      _ptr(ws), ws.numel(), _stream())
+        return tau, st
+
+
+def sample_indices(seed: int, step: int, batch: int, count: int, device="cuda") -> torch.Tensor:
+    out = torch.empty(batch, dtype=torch.int64, device=device)
+    closure_sample_indices(seed, step, batch, count, _ptr(out), _stream())
+    return out

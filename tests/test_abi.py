@@ -102,3 +102,27 @@ def test_calls_on_null_handle_rejected(eles):
     assert eles.lib.filter_set_ygemm(None, 0) == eles.ELES_EINVAL
     for s in range(7):
         assert eles.eles_status_string(s)
+
+
+def test_closure_validation_without_device(eles):
+    import ctypes as C
+    h = C.c_void_p()
+    p = np.zeros(eles.NPARAM, dtype=np.float32)
+    n = np.ones(32)
+    assert eles.closure_state_bytes() > 9414 * 12
+    assert eles.lib.closure_create(None, 1 << 20, p.ctypes.data, n.ctypes.data, None, C.byref(h)) == eles.ELES_EINVAL
+    assert eles.lib.closure_create(0x1000, 16, p.ctypes.data, n.ctypes.data, None, C.byref(h)) == eles.ELES_ENOSPACE
+    bad = p.copy()
+    bad[5] = np.nan
+    big = eles.closure_state_bytes()
+    assert eles.lib.closure_create(0x1000, big, bad.ctypes.data, n.ctypes.data, None, C.byref(h)) == eles.ELES_ENUMERIC
+    n0 = n.copy()
+    n0[12] = 0.0            # a feature with zero spread
+    assert eles.lib.closure_create(0x1000, big, p.ctypes.data, n0.ctypes.data, None, C.byref(h)) == eles.ELES_ENUMERIC
+    assert eles.closure_train_workspace_bytes(33) == 0
+    assert eles.closure_train_workspace_bytes(0) == 0
+    assert eles.closure_train_workspace_bytes(65536) > 65536 * 64
+    assert eles.lib.closure_sample_indices(1, 0, 0, 10, 0x1000, None) == eles.ELES_EINVAL
+    assert eles.lib.closure_infer(None, None, 16, 16, None, 16, 1 << 20, None) == eles.ELES_EINVAL
+    assert eles.lib.closure_step(None) == -1
+    assert eles.closure_blob_bytes() == 3 * 9414 * 4 + 32 * 8 + 8

@@ -1,0 +1,184 @@
+"""GPU parity of the learned closure against the FP64 closure reference."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import closure_ref as C
+from oracle import filter_ref as R
+from paper_1902_02508_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1902_02508_amd import eles
+    return eles
+
+
+def _dev(a, dtype=np.float32):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def _host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _bf16(a):
+    """Round to BF16 (nearest even), returned as float64."""
+    a = np.asarray(a, dtype=np.float32)
+    b = a.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("base,over", [("tiny", {}), ("dns192", dict(nx=40, nz=36, ny=33)),
+                                       ("tiny", dict(nx=15, nz=21, ny=17, ykind="tanh", stretch=2.0))])
+def test_features_match_oracle(E, base, over):
+    cfg = synth.config(base, **over)
+    y, u = synth.make_snapshot(cfg, 2)
+    f = E.Filter.from_config(cfg)
+    ub, _, _ = f.sgs_stress(_dev(u), stats=False)
+    feat = _host(E.features(f, ub))
+    ref = C.features(_host(ub), y, cfg.lx, cfg.lz)
+    for k in range(10):
+        err = _rel(feat[k], ref[k]) if np.linalg.norm(ref[k]) > 0 else np.abs(feat[k]).max()
+        assert err < 1e-4, (k, err)
+
+
+def test_sampler_bit_exact(E):
+    for seed, step, batch, count in ((1, 0, 4096, 1000), (77, 123, 65536, 152_000_000), (5, 9, 33, 7)):
+        gpu = E.sample_indices(seed, step, batch, count).cpu().numpy()
+        ref = C.sample_indices(seed, step, batch, count).astype(np.int64)
+        assert np.array_equal(gpu, ref)
+
+
+def test_moments_match_numpy(E):
+    rng = np.random.default_rng(0)
+    data = (rng.standard_normal((3, 5, 7, 11, 13)) * np.arange(1, 6)[None, :, None, None, None] + 3).astype(np.float32)
+    got = E.moments(_dev(data)).cpu().numpy()
+    mu, sd = C.moments(np.moveaxis(data, 1, 0).reshape(5, -1))
+    assert np.max(np.abs(got[0] - mu)) < 1e-12 * 10 and np.max(np.abs(got[1] - sd) / sd) < 1e-12
+
+
+def _norms(feat, tau):
+    fm, fs = C.moments(np.moveaxis(feat, 0, 0).reshape(10, -1))
+    tm, ts = C.moments(tau.reshape(6, -1))
+    return np.concatenate([fm, fs, tm, ts])
+
+
+def _emulated_forward(theta, xs):
+    """The reference network with the GPU's BF16 roundings of weights and activations."""
+    p = C.unpack(theta)
+    h = _bf16(xs)
+    for l in range(4):
+        W, b = _bf16(p[2 * l]), p[2 * l + 1].astype(np.float32).astype(np.float64)
+        z = h @ W.T + b
+        h = _bf16(C.gelu(z)) if l < 3 else z
+    return h
+
+
+def test_inference_matches_oracle(E):
+    cfg = synth.config("dns192", nx=32, nz=32, ny=33)
+    y, u = synth.make_snapshot(cfg, 4)
+    f = E.Filter.from_config(cfg)
+    ub, tau, _ = f.sgs_stress(_dev(u), stats=False)
+    feat = _host(E.features(f, ub))
+    taun = _host(tau)
+    norms = _norms(feat, taun)
+    theta = C.init_params(11) * 2.0
+    cl = E.Closure(theta, norms)
+    pred, st = cl.infer(f, ub)
+    pred = _host(pred)
+    xs = ((feat.reshape(10, -1).T - norms[:10]) / norms[10:20])
+    ref_std = C.forward(theta.astype(np.float32).astype(np.float64), xs)
+    ref = ref_std * norms[26:32] + norms[20:26]
+    emu = _emulated_forward(theta, xs) * norms[26:32] + norms[20:26]
+    got = pred.reshape(6, -1).T
+    e_exact, e_emu = _rel(got, ref), _rel(got, emu)
+    print(f"inference rel error vs FP64 {e_exact:.2e}, vs BF16 emulation {e_emu:.2e}", flush=True)
+    assert e_emu < 2e-3 and e_exact < 3e-2
+    assert np.allclose(_host(st), pred.mean(axis=(1, 3)), rtol=1e-10, atol=1e-14)
+
+
+def _dataset(E, n_snap=2):
+    cfg = synth.config("dns192", nx=32, nz=32, ny=33)
+    feats, taus = [], []
+    f = E.Filter.from_config(cfg)
+    for s in range(n_snap):
+        y, u = synth.make_snapshot(cfg, 100 + s)
+        ub, tau, _ = f.sgs_stress(_dev(u), stats=False)
+        feats.append(E.features(f, ub).clone())
+        taus.append(tau.clone())
+    import torch
+    return cfg, torch.stack(feats), torch.stack(taus)
+
+
+def test_gradient_matches_oracle(E):
+    """One Adam step with beta1 = beta2 = 0 and a large eps moves every weight
+    by -lr g / (|g| + eps), which is inverted for the gradient g."""
+    cfg, feat, tau = _dataset(E)
+    fh, th = _host(feat), _host(tau)
+    norms = _norms(np.moveaxis(fh, 1, 0), np.moveaxis(th, 1, 0))
+    theta0 = C.init_params(5)
+    cl = E.Closure(theta0, norms)
+    batch, seed, lr, eps = 1024, 42, 1e3, 1e4
+    cl.train(feat, tau, steps=1, batch=batch, seed=seed, lr=lr, beta1=0.0, beta2=0.0, eps=eps)
+    t1 = cl.theta().astype(np.float64)
+    t0 = theta0.astype(np.float32).astype(np.float64)
+    d = t1 - t0
+    g_gpu = -d * eps / (lr - np.abs(d))
+    npts = fh[0, 0].size
+    idx = C.sample_indices(seed, 0, batch, 2 * npts).astype(np.int64)
+    s, p = idx // npts, idx % npts
+    xs = (fh.reshape(2, 10, -1)[s, :, p] - norms[:10]) / norms[10:20]
+    ts = (th.reshape(2, 6, -1)[s, :, p] - norms[20:26]) / norms[26:32]
+    loss, g_ref = C.loss_and_grad(t0, xs, ts)
+    err = _rel(g_gpu, g_ref)
+    print(f"gradient rel L2 error {err:.2e} (loss {loss:.4f})", flush=True)
+    assert err < 2e-2
+
+
+def test_training_tracks_oracle(E):
+    cfg, feat, tau = _dataset(E)
+    fh, th = _host(feat), _host(tau)
+    norms = _norms(np.moveaxis(fh, 1, 0), np.moveaxis(th, 1, 0))
+    theta0 = C.init_params(6)
+    cl = E.Closure(theta0, norms)
+    steps, batch, seed = 150, 512, 3
+    lh = cl.train(feat, tau, steps=steps, batch=batch, seed=seed, lr=1e-3)
+    gpu_loss = lh.cpu().numpy().astype(np.float64)
+    # the reference draws from the same flattened (snapshot, point) index space
+    xs_s = np.concatenate([((fh[s].reshape(10, -1).T - norms[:10]) / norms[10:20]) for s in range(2)])
+    ts_s = np.concatenate([((th[s].reshape(6, -1).T - norms[20:26]) / norms[26:32]) for s in range(2)])
+    _, _, _, ref_loss = C.train(theta0.astype(np.float32).astype(np.float64), xs_s, ts_s, steps, batch, seed)
+    print("loss gpu", gpu_loss[[0, 49, 99, 149]], "ref", ref_loss[[0, 49, 99, 149]], flush=True)
+    assert abs(gpu_loss[0] - ref_loss[0]) < 2e-2 * ref_loss[0]
+    w = 10
+    assert abs(gpu_loss[-w:].mean() - ref_loss[-w:].mean()) < 5e-2 * ref_loss[-w:].mean()
+    assert gpu_loss[-w:].mean() < 0.8 * gpu_loss[:w].mean()
+
+
+def test_checkpoint_resume_is_bit_identical(E):
+    cfg, feat, tau = _dataset(E)
+    fh, th = _host(feat), _host(tau)
+    norms = _norms(np.moveaxis(fh, 1, 0), np.moveaxis(th, 1, 0))
+    a = E.Closure(C.init_params(8), norms)
+    a.train(feat, tau, steps=12, batch=256, seed=9)
+    blob = a.get_params()
+    assert a.step == 12
+    a.train(feat, tau, steps=7, batch=256, seed=9)
+    b = E.Closure(C.init_params(99), norms)
+    b.set_params(blob)
+    assert b.step == 12
+    b.train(feat, tau, steps=7, batch=256, seed=9)
+    assert a.get_params() == b.get_params()
