@@ -1,0 +1,205 @@
+"""The learned-closure experiment: train on exact stresses, judge against them.
+
+    python -m paper_1902_02508_amd.experiment [--train 32] [--heldout 4] [--steps 20000]
+
+Training snapshots (seeded synthetic channel fields) go through the exact
+path (filtered velocity and tau_ij), their gradient features are built on
+the device, and the perceptron is trained on (features -> tau_ij). On
+held-out snapshots the exact tau_ij judges the closure: pointwise relative
+error per component and the relative error of the plane-averaged
+<tau_12>(y) profile in the form of eq. (14) of the paper (full channel and
+the wall-to-centreline half). Two baselines are reported beside it: tau = 0
+and the gradient model tau_ij = sum_k (Delta_k^2 / 12) d_k ubar_i d_k ubar_j
+(the leading term of the small-width expansion of a filtered product). The
+exact path and the closure inference are timed on the same snapshot.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import eles, synth
+
+PAIRS = ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))
+
+
+def trapezoid(y):
+    w = np.empty(len(y))
+    w[1:-1] = 0.5 * (y[2:] - y[:-2])
+    w[0] = 0.5 * (y[1] - y[0])
+    w[-1] = 0.5 * (y[-1] - y[-2])
+    return w
+
+
+def profile_error(a, b, y, half=False):
+    """sqrt(int (a - b)^2 dy / int b^2 dy), trapezoid rule; half: lower wall to centreline."""
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    if half:
+        k = y <= 0.0
+        y, a, b = y[k], a[k], b[k]
+    w = trapezoid(y)
+    return math.sqrt(np.sum(w * (a - b) ** 2) / np.sum(w * b * b))
+
+
+def init_params(seed: int) -> np.ndarray:
+    """U(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases from PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for a, b in zip((10, 64, 64, 64), (64, 64, 64, 6)):
+        lim = 1.0 / math.sqrt(a)
+        parts.append(rng.uniform(-lim, lim, size=(b, a)).ravel())
+        parts.append(rng.uniform(-lim, lim, size=(b,)))
+    return np.concatenate(parts)
+
+
+def exact_snapshot(f, cfg, seed, dev):
+    y, u = synth.make_snapshot(cfg, seed)
+    du = torch.from_numpy(u).to(dev)
+    ub, tau, st = f.sgs_stress(du)
+    return du, ub, tau, st
+
+
+def build_dataset(f, cfg, seeds, dev, log=print):
+    feats = torch.empty((len(seeds), 10) + f.shape, dtype=torch.float32, device=dev)
+    taus = torch.empty((len(seeds), 6) + f.shape, dtype=torch.float32, device=dev)
+    for k, s in enumerate(seeds):
+        du, ub, tau, _ = exact_snapshot(f, cfg, s, dev)
+        eles.features(f, ub, out=feats[k])
+        taus[k].copy_(tau)
+        del du, ub, tau
+    torch.cuda.synchronize()
+    log(f"dataset: {len(seeds)} snapshots of {cfg.nx}x{cfg.ny}x{cfg.nz}")
+    return feats, taus
+
+
+def gradient_model(feat: np.ndarray, cfg) -> np.ndarray:
+    """tau_ij ~ sum_k (Delta_k^2/12) d_k ubar_i d_k ubar_j from the feature field [10][...]."""
+    d2 = (cfg.delta_x ** 2 / 12.0, cfg.delta_y ** 2 / 12.0, cfg.delta_z ** 2 / 12.0)
+    out = np.zeros((6,) + feat.shape[1:])
+    for q, (i, j) in enumerate(PAIRS):
+        for k in range(3):
+            out[q] += d2[k] * feat[3 * i + k].astype(np.float64) * feat[3 * j + k]
+    return out
+
+
+def evaluate(cl, f, cfg, seeds, dev):
+    """Closure and baselines against the exact stress on held-out snapshots (host-side metrics)."""
+    y = synth.ygrid(cfg.ny, cfg.ykind, cfg.stretch)
+    w = trapezoid(y)
+    rows = []
+    for s in seeds:
+        du, ub, tau, st = exact_snapshot(f, cfg, s, dev)
+        pred, pst = cl.infer(f, ub)
+        feat = eles.features(f, ub)
+        torch.cuda.synchronize()
+        ref = tau.cpu().numpy().astype(np.float64)
+        got = pred.cpu().numpy().astype(np.float64)
+        gm = gradient_model(feat.cpu().numpy(), cfg)
+        ref12 = st[4].cpu().numpy()                  # <tau_12>(y), FP64 plane sums of the exact path
+        ml12 = pst[1].cpu().numpy()                  # <tau_12>(y) of the closure
+        gm12 = gm[1].mean(axis=(0, 2))
+        point = []
+        for q in range(6):
+            num = np.mean((got[q] - ref[q]) ** 2, axis=(0, 2))
+            den = np.mean(ref[q] ** 2, axis=(0, 2))
+            point.append(math.sqrt(np.sum(w * num) / np.sum(w * den)))
+        rows.append({
+            "seed": s,
+            "tau12_profile_error": profile_error(ml12, ref12, y),
+            "tau12_profile_error_half": profile_error(ml12, ref12, y, half=True),
+            "tau12_profile_error_gradient_model": profile_error(gm12, ref12, y),
+            "pointwise_rel_l2": point,
+        })
+        del du, ub, tau, pred, feat
+    return rows
+
+
+def time_paths(cl, f, cfg, dev, reps=20):
+    y, u = synth.make_snapshot(cfg, synth.SEEDS["heldout"][0])
+    du = torch.from_numpy(u).to(dev)
+    ub = torch.empty((3,) + f.shape, dtype=torch.float32, device=dev)
+    tau = torch.empty((6,) + f.shape, dtype=torch.float32, device=dev)
+    st = torch.empty((9, cfg.ny), dtype=torch.float64, device=dev)
+    pred = torch.empty_like(tau)
+    pst = torch.empty((6, cfg.ny), dtype=torch.float64, device=dev)
+    for _ in range(3):
+        f.sgs_stress(du, ub, tau, st)
+        cl.infer(f, ub, pred, pst)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        f.sgs_stress(du, ub, tau, st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        cl.infer(f, ub, pred, pst)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    exact = cfg.points * reps / (t1 - t0)
+    learned = cfg.points * reps / (t2 - t1)
+    return {"exact_points_per_s": exact, "closure_points_per_s": learned, "speedup": learned / exact}
+
+
+def run(n_train=32, n_heldout=4, steps=20000, batch=65536, lr=1e-3, seed=1, workload="dns192",
+        tail=1e-8, log=print):
+    dev = torch.device("cuda", torch.cuda.current_device())
+    cfg = synth.config(workload)
+    f = eles.Filter.from_config(cfg, tail_tol=tail, device=dev)
+    t0 = time.perf_counter()
+    feats, taus = build_dataset(f, cfg, synth.SEEDS["train"][:n_train], dev, log)
+    fm = eles.moments(feats).cpu().numpy()
+    tm = eles.moments(taus).cpu().numpy()
+    norms = np.concatenate([fm[0], fm[1], tm[0], tm[1]])
+    cl = eles.Closure(init_params(seed), norms, device=dev)
+    t1 = time.perf_counter()
+    chunks = []
+    done = 0
+    while done < steps:
+        n = min(2000, steps - done)
+        chunks.append(cl.train(feats, taus, steps=n, batch=batch, seed=seed, lr=lr))
+        torch.cuda.synchronize()
+        done += n
+        log(f"  {done} steps, {time.perf_counter() - t1:.1f} s, loss {chunks[-1][-50:].mean().item():.4f}")
+    t2 = time.perf_counter()
+    lh = torch.cat(chunks).cpu().numpy()
+    log(f"trained {steps} steps of {batch} in {t2 - t1:.2f} s; loss {lh[:10].mean():.4f} -> {lh[-100:].mean():.4f}")
+    del feats, taus
+    torch.cuda.empty_cache()
+    rows = evaluate(cl, f, cfg, synth.SEEDS["heldout"][:n_heldout], dev)
+    speed = time_paths(cl, f, cfg, dev)
+    res = {
+        "workload": f"channel {cfg.nx}x{cfg.ny}x{cfg.nz}",
+        "train_snapshots": n_train, "heldout_snapshots": n_heldout, "steps": steps, "batch": batch,
+        "train_seconds": t2 - t1, "dataset_seconds": t1 - t0,
+        "loss_first": float(lh[:10].mean()), "loss_last": float(lh[-100:].mean()),
+        "tau12_profile_error": float(np.mean([r["tau12_profile_error"] for r in rows])),
+        "tau12_profile_error_half": float(np.mean([r["tau12_profile_error_half"] for r in rows])),
+        "tau12_profile_error_gradient_model": float(np.mean([r["tau12_profile_error_gradient_model"] for r in rows])),
+        "pointwise_rel_l2": [float(np.mean([r["pointwise_rel_l2"][q] for r in rows])) for q in range(6)],
+        **speed,
+    }
+    return res, cl, f
+
+
+def main(argv=None):
+    p = argparse.ArgumentParser()
+    p.add_argument("--train", type=int, default=32)
+    p.add_argument("--heldout", type=int, default=4)
+    p.add_argument("--steps", type=int, default=20000)
+    p.add_argument("--batch", type=int, default=65536)
+    p.add_argument("--lr", type=float, default=1e-3)
+    p.add_argument("--seed", type=int, default=1)
+    a = p.parse_args(argv)
+    res, _, _ = run(a.train, a.heldout, a.steps, a.batch, a.lr, a.seed,
+                    log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
