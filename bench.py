@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "points/s for filt(u_i)+tau_ij filtering; MLP-closure speedup at stated tau error"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP32_VALU_PEAK_TF = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, packed FP32 off
+FP32_VALU_PEAK_TF = 157.3      # MI355X vector FP32; reached by non-packed v_fma_f32 on gfx950
 FP32_MFMA_PEAK_TF = 157.3      # dense FP32 matrix rate
 BF16_MFMA_PEAK_TF = 2500.0     # dense BF16 matrix rate
 

@@ -756,7 +756,9 @@ int32_t closure_train(eles_closure c, const float *feat, const float *tau, int32
   return ELES_OK;
 }
 
-size_t closure_infer_workspace_bytes(eles_filter f) { return f ? up256(10 * f->npts * 4) : 0; }
+size_t closure_infer_workspace_bytes(eles_filter f) {
+  return f ? up256(10 * f->npts * 4) + up256((size_t)eles::plane_mean_parts(6, f->d.ny) * 8) : 0;
+}
 
 int32_t closure_infer(eles_closure c, eles_filter f, const float *ubar, float *tau_pred, double *stats, void *ws,
                       size_t ws_bytes, hipStream_t stream) {
@@ -770,7 +772,9 @@ int32_t closure_infer(eles_closure c, eles_filter f, const float *ubar, float *t
   int32_t st = closure_features(f, ubar, feat, stream);
   if (st != ELES_OK) return st;
   if (eles::launch_infer(c->c, feat, (long)n, tau_pred, stream) != hipSuccess) return ELES_EHIP;
-  if (stats && eles::launch_plane_mean(tau_pred, 6, f->d.nx, f->d.ny, f->d.nz, stats, stream) != hipSuccess)
+  double *part = (double *)((char *)ws + up256(10 * n * 4));
+  if (stats &&
+      eles::launch_plane_mean(tau_pred, 6, f->d.nx, f->d.ny, f->d.nz, part, stats, stream) != hipSuccess)
     return ELES_EHIP;
   return ELES_OK;
 }

@@ -10,7 +10,8 @@
 // are kept in both orientations so the weight gradients reduce over the
 // batch as contiguous K, and split-K partials are summed in a fixed order by
 // the Adam kernel. Inference runs all four layers of a 16-point tile inside
-// one wave, activations staying in registers and a 2 KB LDS transpose.
+// one wave, weights held in registers, activations through a 2 KB LDS
+// transpose.
 #include "k_gemm.cuh"
 
 namespace eles {
@@ -19,9 +20,32 @@ namespace {
 constexpr int H = kMlpHidden;
 constexpr int K1 = kMlpInPad;
 
-__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU(x) = x Phi(x) evaluated without transcendentals: max(x, 0) - h(s),
+// s = min(|x|, 4), h(s) = sum_k c_k s^k (k = 1..7) fitted to s Phi(-s) with
+// c_1 = 1/2; within 2.4e-4 of x Phi(x), below the BF16 resolution of the
+// activations, and free of the branches of an erf evaluation.
+__device__ inline float gelu_h(float s) {
+  float h = -0.0006385124288499355f;
+  h = fmaf(h, s, 0.009885221719741821f);
+  h = fmaf(h, s, -0.05751597508788109f);
+  h = fmaf(h, s, 0.14029717445373535f);
+  h = fmaf(h, s, -0.04402020201086998f);
+  h = fmaf(h, s, -0.3894234895706177f);
+  h = fmaf(h, s, 0.5f);
+  return h * s;
+}
+__device__ inline float gelu(float z) { return fmaxf(z, 0.0f) - gelu_h(fminf(fabsf(z), 4.0f)); }
 __device__ inline float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+  const float s = fabsf(z);
+  float d = 7.0f * -0.0006385124288499355f;
+  d = fmaf(d, s, 6.0f * 0.009885221719741821f);
+  d = fmaf(d, s, 5.0f * -0.05751597508788109f);
+  d = fmaf(d, s, 4.0f * 0.14029717445373535f);
+  d = fmaf(d, s, 3.0f * -0.04402020201086998f);
+  d = fmaf(d, s, 2.0f * -0.3894234895706177f);
+  d = fmaf(d, s, 0.5f);
+  d = s < 4.0f ? d : 0.0f;
+  return z >= 0.0f ? 1.0f - d : d;
 }
 
 __device__ inline uint64_t splitmix64(uint64_t seed, uint64_t n) {
@@ -226,29 +250,45 @@ __device__ inline void write_shadow(const ClosureView &c, const ParamLoc &L, flo
 }
 
 // Sum the split-K partials of every gradient in a fixed order, then apply
-// one Adam step; thread 0 also totals the loss of the step.
+// one Adam step. Eight lanes share a parameter: lane j adds chunks j, j+8,
+// ... in order and the eight sums are combined by a fixed butterfly. The
+// last block totals the loss of the step.
+constexpr int kAdamLanes = 8;
+constexpr int kAdamPerBlock = 256 / kAdamLanes;
+
 __global__ void __launch_bounds__(256) k_adam(ClosureView c, AdamArgs a) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p == 0 && a.loss_out) {
+  __shared__ double red[256];
+  if (blockIdx.x == gridDim.x - 1) {
     double s = 0.0;
-    for (int w = 0; w < a.nloss; ++w) s += a.lossp[w];
-    a.loss_out[0] = (float)(s / ((double)a.batch * kMlpOut));
+    for (int w = threadIdx.x; w < a.nloss; w += 256) s += a.lossp[w];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && a.loss_out) a.loss_out[0] = (float)(red[0] / ((double)a.batch * kMlpOut));
+    return;
   }
-  if (p >= kMlpNParam) return;
-  const ParamLoc L = locate(p);
-  const int fin[4] = {kMlpIn, H, H, H};
-  const int fout[4] = {H, H, H, kMlpOut};
+  const int sub = threadIdx.x % kAdamLanes;
+  const int p = blockIdx.x * kAdamPerBlock + threadIdx.x / kAdamLanes;
+  const bool live = p < kMlpNParam;
+  const ParamLoc L = locate(live ? p : 0);
   const int M = a.mrows[L.layer], N = a.ncols[L.layer];
-  (void)fout;
   double gsum = 0.0;
   if (L.bias) {
-    const float *pb = a.pb[L.layer];
-    for (int ch = 0; ch < a.nchunks; ++ch) gsum += pb[(long)ch * M + L.n];
+    const float *pb = a.pb[L.layer] + L.n;
+#pragma unroll 4
+    for (int ch = sub; ch < a.nchunks; ch += kAdamLanes) gsum += pb[(long)ch * M];
   } else {
-    const float *pw = a.pw[L.layer];
-    for (int ch = 0; ch < a.nchunks; ++ch) gsum += pw[((long)ch * M + L.n) * N + L.k];
+    const float *pw = a.pw[L.layer] + (long)L.n * N + L.k;
+#pragma unroll 4
+    for (int ch = sub; ch < a.nchunks; ch += kAdamLanes) gsum += pw[(long)ch * M * N];
   }
-  (void)fin;
+  gsum += __shfl_xor(gsum, 1);
+  gsum += __shfl_xor(gsum, 2);
+  gsum += __shfl_xor(gsum, 4);
+  if (!live || sub != 0) return;
   const float g = (float)gsum;
   const float m = a.b1 * c.m[p] + (1.0f - a.b1) * g;
   const float v = a.b2 * c.v[p] + (1.0f - a.b2) * g * g;
@@ -268,21 +308,24 @@ __global__ void __launch_bounds__(256) k_shadows(ClosureView c) {
 
 // -------------------------------------------------------------- inference
 
-constexpr int kInferBlocks = 2048;
+constexpr int kInferWavesPerCu = 12;
 
-// All four layers of 16-point tiles; the weights sit in LDS, activations of
-// a tile go through a per-wave 16 x 64 BF16 transpose.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// All four layers of 16-point tiles. Each wave keeps its A fragments of W1,
+// W2 and W4 in registers for the whole run (W3 is read from LDS) and loops
+// over tiles, fetching the next tile's features while the current one is
+// computed; a tile's activations go through a per-wave 16 x 64 BF16 LDS
+// transpose between layers.
 __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__restrict__ feat, long npts,
                                                float *__restrict__ out) {
-  __shared__ __attribute__((aligned(16))) uint16_t sw1[H * K1], sw2[H * H], sw3[H * H], sw4[16 * H];
   __shared__ float sb[3 * H + 16];
+  __shared__ __attribute__((aligned(16))) uint16_t sw3[H * H];
   __shared__ __attribute__((aligned(16))) uint16_t sh[4][16 * H];
-  for (int i = threadIdx.x; i < H * K1; i += 256) sw1[i] = c.w1[i];
-  for (int i = threadIdx.x; i < H * H; i += 256) {
-    sw2[i] = c.w2[i];
-    sw3[i] = c.w3[i];
-  }
-  for (int i = threadIdx.x; i < 16 * H; i += 256) sw4[i] = c.w4[i];
   for (int i = threadIdx.x; i < 3 * H + 16; i += 256) {
     float b = 0.0f;
     if (i < H) b = c.theta[kMlpOffB1 + i];
@@ -291,62 +334,55 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
     else if (i - 3 * H < kMlpOut) b = c.theta[kMlpOffB4 + i - 3 * H];
     sb[i] = b;
   }
+  for (int i = threadIdx.x; i < H * H / 8; i += 256)
+    reinterpret_cast<gus8 *>(sw3)[i] = reinterpret_cast<const gus8 *>(c.w3)[i];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, grp = lane >> 4;
   uint16_t *hs = sh[wave];
+  gus8 a1[4], a2[4][2], a4[2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    a1[t] = *reinterpret_cast<const gus8 *>(c.w1 + (16 * t + col) * K1 + 8 * grp);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      a2[t][s] = *reinterpret_cast<const gus8 *>(c.w2 + (16 * t + col) * H + 32 * s + 8 * grp);
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s) a4[s] = *reinterpret_cast<const gus8 *>(c.w4 + col * H + 32 * s + 8 * grp);
+  // lane (point col, group grp) carries features 8 grp .. 8 grp + 7
+  const int nf = grp == 0 ? 8 : (grp == 1 ? kMlpIn - 8 : 0);
+  float fsc[8], fsh[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    fsc[e] = e < nf ? c.fsc[8 * grp + e] : 0.0f;
+    fsh[e] = e < nf ? c.fsh[8 * grp + e] : 0.0f;
+  }
   const long ntile = (npts + 15) / 16;
-  for (long tile = (long)blockIdx.x * 4 + wave; tile < ntile; tile += (long)gridDim.x * 4) {
+  const long stride = (long)gridDim.x * 4;
+  float fv[8];
+  auto fetch = [&](long tile) {
+    const long p = tile * 16 + col;
+    const bool ok = tile < ntile && p < npts;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) fv[e] = (ok && e < nf) ? feat[(long)(8 * grp + e) * npts + p] : 0.0f;
+  };
+  long tile = (long)blockIdx.x * 4 + wave;
+  fetch(tile);
+  for (; tile < ntile; tile += stride) {
     const long p = tile * 16 + col;
     const bool pok = p < npts;
-    // standardised features of point p, features 8 grp .. 8 grp + 7
-    gus8 xb = gus8{0, 0, 0, 0, 0, 0, 0, 0};
+    gus8 xb;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int f = 8 * grp + e;
-      if (f < kMlpIn && pok) xb[e] = g_bf16(feat[(long)f * npts + p] * c.fsc[f] + c.fsh[f]);
-    }
-    gus8 bk[2];
-    // layer 1: K = 32 (one step)
-    {
-      gf4 acc[4];
+    for (int e = 0; e < 8; ++e) xb[e] = e < nf ? g_bf16(fv[e] * fsc[e] + fsh[e]) : (unsigned short)0;
+    fetch(tile + stride);
+    gf4 acc[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const gus8 aw = *reinterpret_cast<const gus8 *>(sw1 + (16 * t + col) * K1 + 8 * grp);
-        acc[t] = g_mma(aw, xb, gf4{0.f, 0.f, 0.f, 0.f});
-      }
+    for (int t = 0; t < 4; ++t) acc[t] = g_mma(a1[t], xb, gf4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        uint16_t hv[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) hv[r] = g_bf16(gelu(acc[t][r] + sb[16 * t + 4 * grp + r]));
-        *reinterpret_cast<uint2 *>(hs + col * H + 16 * t + 4 * grp) =
-            make_uint2(hv[0] | ((uint32_t)hv[1] << 16), hv[2] | ((uint32_t)hv[3] << 16));
-      }
-    }
-    // layers 2 and 3: K = 64 (two steps)
-#pragma unroll
-    for (int l = 0; l < 2; ++l) {
-      const uint16_t *sw = l == 0 ? sw2 : sw3;
-      const float *bb = sb + (l + 1) * H;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-      for (int s = 0; s < 2; ++s) bk[s] = *reinterpret_cast<const gus8 *>(hs + col * H + 32 * s + 8 * grp);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      gf4 acc[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        acc[t] = gf4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const gus8 aw = *reinterpret_cast<const gus8 *>(sw + (16 * t + col) * H + 32 * s + 8 * grp);
-          acc[t] = g_mma(aw, bk[s], acc[t]);
-        }
-      }
+    for (int l = 0; l < 3; ++l) {
+      // bias and GELU of layer l, transposed through LDS into the next B operand
+      const float *bb = sb + l * H;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         uint16_t hv[4];
@@ -355,26 +391,32 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
         *reinterpret_cast<uint2 *>(hs + col * H + 16 * t + 4 * grp) =
             make_uint2(hv[0] | ((uint32_t)hv[1] << 16), hv[2] | ((uint32_t)hv[3] << 16));
       }
-    }
-    // output layer
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      wave_sync();
+      gus8 bk[2];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) bk[s] = *reinterpret_cast<const gus8 *>(hs + col * H + 32 * s + 8 * grp);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    gf4 acc = gf4{0.f, 0.f, 0.f, 0.f};
+      for (int s = 0; s < 2; ++s) bk[s] = *reinterpret_cast<const gus8 *>(hs + col * H + 32 * s + 8 * grp);
+      wave_sync();
+      if (l < 2) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const gus8 aw = *reinterpret_cast<const gus8 *>(sw4 + col * H + 32 * s + 8 * grp);
-      acc = g_mma(aw, bk[s], acc);
-    }
+        for (int t = 0; t < 4; ++t) {
+          acc[t] = gf4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int o = 4 * grp + r;
-      if (o < kMlpOut && pok) out[(long)o * npts + p] = (acc[r] + sb[3 * H + o]) * c.isc[o] + c.ish[o];
+          for (int s = 0; s < 2; ++s) {
+            const gus8 aw = l == 0 ? a2[t][s]
+                                   : *reinterpret_cast<const gus8 *>(sw3 + (16 * t + col) * H + 32 * s + 8 * grp);
+            acc[t] = g_mma(aw, bk[s], acc[t]);
+          }
+        }
+      } else {
+        gf4 y = gf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) y = g_mma(a4[s], bk[s], y);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int o = 4 * grp + r;
+          if (o < kMlpOut && pok) out[(long)o * npts + p] = (y[r] + sb[3 * H + o]) * c.isc[o] + c.ish[o];
+        }
+      }
     }
   }
 }
@@ -415,15 +457,20 @@ __global__ void k_mom_final(const double *part, int nchunks, int nchan, double c
     out[nchan + c] = sqrt(s / count);
 }
 
-// <f_q>(y_j) over x and z for planar fields [nq][nx][ny][nz], FP64 sums.
-__global__ void __launch_bounds__(256) k_plane_mean(const float *f, int nx, int ny, int nz, double *out) {
+// <f_q>(y_j) over x and z for planar fields [nq][nx][ny][nz], FP64 sums:
+// each block adds an x-range of one (q, j) plane, a second kernel adds the
+// kPlaneSplit partial sums in order.
+constexpr int kPlaneSplit = 16;
+
+__global__ void __launch_bounds__(256) k_plane_part(const float *f, int nx, int ny, int nz, double *part) {
   __shared__ double red[256];
-  const int j = blockIdx.x, q = blockIdx.y;
-  const long cnt = (long)nx * nz;
+  const int j = blockIdx.x, q = blockIdx.y, sp = blockIdx.z;
+  const int xb = (int)((long)nx * sp / kPlaneSplit), xe = (int)((long)nx * (sp + 1) / kPlaneSplit);
+  const long cnt = (long)(xe - xb) * nz;
   const float *base = f + (long)q * nx * ny * nz;
   double s = 0.0;
   for (long t = threadIdx.x; t < cnt; t += 256) {
-    const long x = t / nz, z = t % nz;
+    const long x = xb + t / nz, z = t % nz;
     s += (double)base[(x * ny + j) * nz + z];
   }
   red[threadIdx.x] = s;
@@ -432,7 +479,15 @@ __global__ void __launch_bounds__(256) k_plane_mean(const float *f, int nx, int 
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[(long)q * ny + j] = red[0] / (double)cnt;
+  if (threadIdx.x == 0) part[((long)q * ny + j) * kPlaneSplit + sp] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_plane_final(const double *part, int n, double inv, double *out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int sp = 0; sp < kPlaneSplit; ++sp) s += part[(long)i * kPlaneSplit + sp];
+  out[i] = s * inv;
 }
 
 }  // namespace
@@ -452,7 +507,8 @@ hipError_t launch_shadows(const ClosureView &c, hipStream_t s) {
 hipError_t launch_infer(const ClosureView &c, const float *feat, long npts, float *out, hipStream_t s) {
   const long tiles = (npts + 15) / 16;
   long blocks = (tiles + 3) / 4;
-  if (blocks > kInferBlocks) blocks = kInferBlocks;
+  const long cap = 256L * kInferWavesPerCu / 4;   // every wave keeps its weights for many tiles
+  if (blocks > cap) blocks = cap;
   k_infer<<<(unsigned)blocks, 256, 0, s>>>(c, feat, npts, out);
   return hipGetLastError();
 }
@@ -468,8 +524,12 @@ hipError_t launch_moments(const float *data, int nchan, int nsnap, long npts, do
   return hipGetLastError();
 }
 
-hipError_t launch_plane_mean(const float *f, int nq, int nx, int ny, int nz, double *out, hipStream_t s) {
-  k_plane_mean<<<dim3(ny, nq), 256, 0, s>>>(f, nx, ny, nz, out);
+hipError_t launch_plane_mean(const float *f, int nq, int nx, int ny, int nz, double *part, double *out,
+                             hipStream_t s) {
+  k_plane_part<<<dim3(ny, nq, kPlaneSplit), 256, 0, s>>>(f, nx, ny, nz, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_plane_final<<<(nq * ny + 255) / 256, 256, 0, s>>>(part, nq * ny, 1.0 / ((double)nx * nz), out);
   return hipGetLastError();
 }
 
@@ -560,7 +620,7 @@ hipError_t launch_train_step(const ClosureView &c, const TrainData &d, const Tra
     adam.mrows[l] = mrows[l];
     adam.ncols[l] = ncols[l];
   }
-  k_adam<<<(kMlpNParam + 255) / 256, 256, 0, s>>>(c, adam);
+  k_adam<<<(kMlpNParam + kAdamPerBlock - 1) / kAdamPerBlock + 1, 256, 0, s>>>(c, adam);
   return hipGetLastError();
 }
 
