@@ -104,17 +104,21 @@ def evaluate(cl, f, cfg, seeds, dev):
         ref12 = st[4].cpu().numpy()                  # <tau_12>(y), FP64 plane sums of the exact path
         ml12 = pst[1].cpu().numpy()                  # <tau_12>(y) of the closure
         gm12 = gm[1].mean(axis=(0, 2))
-        point = []
+        point, point_gm = [], []
         for q in range(6):
-            num = np.mean((got[q] - ref[q]) ** 2, axis=(0, 2))
-            den = np.mean(ref[q] ** 2, axis=(0, 2))
-            point.append(math.sqrt(np.sum(w * num) / np.sum(w * den)))
+            den = np.sum(w * np.mean(ref[q] ** 2, axis=(0, 2)))
+            point.append(math.sqrt(np.sum(w * np.mean((got[q] - ref[q]) ** 2, axis=(0, 2))) / den))
+            point_gm.append(math.sqrt(np.sum(w * np.mean((gm[q] - ref[q]) ** 2, axis=(0, 2))) / den))
+        # size of the mean profile relative to the pointwise field
+        prof_ratio = math.sqrt(np.sum(w * ref12 ** 2) / np.sum(w * np.mean(ref[1] ** 2, axis=(0, 2))))
         rows.append({
             "seed": s,
             "tau12_profile_error": profile_error(ml12, ref12, y),
             "tau12_profile_error_half": profile_error(ml12, ref12, y, half=True),
             "tau12_profile_error_gradient_model": profile_error(gm12, ref12, y),
             "pointwise_rel_l2": point,
+            "pointwise_rel_l2_gradient_model": point_gm,
+            "tau12_profile_to_field_ratio": prof_ratio,
         })
         del du, ub, tau, pred, feat
     return rows
@@ -182,6 +186,9 @@ def run(n_train=32, n_heldout=4, steps=20000, batch=65536, lr=1e-3, seed=1, work
         "tau12_profile_error_half": float(np.mean([r["tau12_profile_error_half"] for r in rows])),
         "tau12_profile_error_gradient_model": float(np.mean([r["tau12_profile_error_gradient_model"] for r in rows])),
         "pointwise_rel_l2": [float(np.mean([r["pointwise_rel_l2"][q] for r in rows])) for q in range(6)],
+        "pointwise_rel_l2_gradient_model": [float(np.mean([r["pointwise_rel_l2_gradient_model"][q] for r in rows]))
+                                            for q in range(6)],
+        "tau12_profile_to_field_ratio": float(np.mean([r["tau12_profile_to_field_ratio"] for r in rows])),
         **speed,
     }
     return res, cl, f
