@@ -34,9 +34,11 @@
  * *_destroy frees host memory only.
  *
  * Execution. Every call enqueues work on the given stream and returns
- * without waiting for it, except filter_setup, which also copies the host
- * y array to the device. One handle must not be used from two streams or
- * threads at once. All device pointers must be 16-byte aligned.
+ * without waiting for it, except filter_setup, which copies the host y
+ * array to the device, builds the operators and waits for the stream (it
+ * reads the operators' band structure back to plan the y pass). One handle
+ * must not be used from two streams or threads at once. All device
+ * pointers must be 16-byte aligned.
  *
  * Errors. Arguments are validated before anything is enqueued; a failing
  * call returns a non-zero eles_status and enqueues nothing. A HIP error
@@ -92,6 +94,10 @@ typedef struct {
   size_t off_shift;            /* FP64 [3][ny]: m, M = W^+ m, W^+ m^2 - M^2
                                   of the last sgs_stress call                  */
   size_t state_bytes;
+  int32_t y_groups;            /* row groups of the LDS-staged FP32 stress y
+                                  pass; 0 when this grid uses the direct
+                                  y pass instead                              */
+  int32_t y_blocks;            /* persistent blocks of the staged y pass      */
 } eles_state_layout;
 
 /* Human-readable name of a status code. Never NULL. */

@@ -5,6 +5,7 @@
 #include "eles.h"
 #include "eles_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -19,6 +20,8 @@ struct eles_filter_s {
   eles_state_layout lay;
   int zt, nzt, nxt, n16;
   size_t npts;
+  bool ys_ok;          // the staged stress y pass fits this grid
+  eles::YsPlan ys;
   // per-pass event timing
   int prof_max = 0, prof_calls = 0;
   std::vector<hipEvent_t> ev;   // [call][pass][start, stop]
@@ -173,10 +176,92 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
   return pa < pb + nb && pb < pa + na;
 }
 
+// Groups of consecutive 16-row tiles for the staged stress y pass, from the
+// operators' row bands. A tile walks its K range [lo, hi) in chunks of 16
+// from k0 = lo rounded down to 4, moved down (not below 0) so that the walk
+// ends by ny rounded up to 4 where it can; a group stages the union of its
+// tiles' walks (rows past ny as zeros), next to its products and its
+// operator tiles (4 KiB per chunk). Groups grow to maxt tiles
+// while the block's LDS stays within budget; false if no plan fits.
+bool plan_ys_groups(const std::vector<int> &rb, int ny, int maxt, size_t budget, eles::YsPlan *out) {
+  const int ntile = (ny + 15) / 16;
+  const int e = (ny + 3) & ~3;
+  std::vector<int> k0(ntile), nc(ntile);
+  for (int t = 0; t < ntile; ++t) {
+    int lo = 1 << 30, hi = 0;
+    for (int r = 0; r < 16; ++r) {
+      const int a = rb[2 * (16 * t + r)], b = rb[2 * (16 * t + r) + 1];
+      if (b > a) {
+        lo = std::min(lo, a);
+        hi = std::max(hi, b);
+      }
+    }
+    if (hi == 0) lo = 0;
+    int s = lo & ~3;
+    const int n = (hi - s + 15) >> 4;
+    if (s + 16 * n > e) s = std::max(0, e - 16 * n);
+    k0[t] = s;
+    nc[t] = n;
+  }
+  eles::YsPlan p;
+  std::memset(&p, 0, sizeof(p));
+  auto bytes = [](int chunks, int rows) {
+    eles::YsPlan q;
+    q.max_chunks = chunks;
+    q.lds_rows = rows;
+    return eles::ys_lds_bytes(q);
+  };
+  int nchunk = 0;
+  for (int t = 0; t < ntile;) {
+    if (p.ngroup == eles::kYsMaxGroups) return false;
+    const int start = t;
+    int kb = 1 << 30, kend = 0, rows = 0, chunks = 0;
+    while (t < ntile && t - start < maxt) {
+      const int nkb = std::min(kb, k0[t]), nke = std::max(kend, k0[t] + 16 * nc[t]);
+      const int nrows = nke - nkb;
+      const int nch = chunks + nc[t];
+      if (t > start && (nch > eles::kYsMaxGroupChunks ||
+                        bytes(std::max(p.max_chunks, nch), std::max(p.lds_rows, nrows)) > budget))
+        break;
+      kb = nkb;
+      kend = nke;
+      rows = nrows;
+      chunks = nch;
+      ++t;
+    }
+    if (nchunk + chunks > eles::kYsMaxChunks || chunks > eles::kYsMaxGroupChunks) return false;
+    const int g = p.ngroup++;
+    p.tile0[g] = start;
+    p.ntile[g] = t - start;
+    p.kb[g] = kb;
+    p.nrow[g] = kend - kb;
+    p.chunk0[g] = nchunk;
+    p.nchunk[g] = chunks;
+    for (int u = start; u < t; ++u)
+      for (int c = 0; c < nc[u]; ++c)
+        p.chunk[nchunk++] = (k0[u] + 16 * c) | ((u - start) << 16) | ((c == nc[u] - 1) << 24);
+    p.max_chunks = std::max(p.max_chunks, chunks);
+    p.lds_rows = std::max(p.lds_rows, rows);
+  }
+  if (eles::ys_lds_bytes(p) > budget) return false;
+  *out = p;
+  return true;
+}
+
+// Plane partials per (quantity, row): one per block of a group on the
+// staged path, one per (x, 64-column block) on the other.
+int sgs_parts(const eles_filter_s *f, bool staged) {
+  return staged ? f->ys.nblk / f->ys.ngroup : eles::y_parts(f->d.nx, f->n16);
+}
+
+// Workspace of sgs_stress: the nine x/z-filtered fields, then the plane
+// partials.
 size_t sgs_ws(const eles_filter_s *f, size_t *off_part) {
   const size_t x = up256(9 * f->npts * sizeof(float));
+  int parts = sgs_parts(f, false);
+  if (f->ys_ok) parts = std::max(parts, sgs_parts(f, true));
   if (off_part) *off_part = x;
-  return x + up256((size_t)9 * f->d.ny * eles::y_parts(f->d.nx, f->n16) * sizeof(double));
+  return x + up256((size_t)9 * f->d.ny * parts * sizeof(double));
 }
 
 eles::YArgs y_args(const eles_filter_s *f) {
@@ -235,7 +320,7 @@ void end_call(eles_filter_s *f) {
 
 void release_events(eles_filter_s *f) {
   for (hipEvent_t e : f->ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   f->ev.clear();
   f->used.clear();
   f->prof_max = f->prof_calls = 0;
@@ -304,6 +389,23 @@ int32_t filter_setup(const eles_filter_desc *desc, void *state, size_t state_byt
     delete f;
     return ELES_EHIP;
   }
+  // the y-pass plan needs the operators' row bands on the host
+  std::vector<int> rb(2 * (size_t)p.mpad);
+  if (hipMemcpyAsync(rb.data(), f->v.rowband, rb.size() * sizeof(int), hipMemcpyDeviceToHost, stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    delete f;
+    return ELES_EHIP;
+  }
+  f->ys_ok = false;
+  for (size_t budget : {eles::kYsLdsMax}) {
+    if (!plan_ys_groups(rb, desc->ny, eles::kYsMaxTiles, budget, &f->ys)) continue;
+    f->ys.nblk = eles::ys_grid(f->ys, desc->nz, desc->nx * f->n16);
+    f->ys_ok = f->ys.nblk > 0;
+    break;
+  }
+  L.y_groups = f->ys_ok ? f->ys.ngroup : 0;
+  L.y_blocks = f->ys_ok ? f->ys.nblk : 0;
   *out = f;
   return ELES_OK;
 }
@@ -404,11 +506,14 @@ int32_t sgs_stress(eles_filter f, const float *u, float *ubar, float *tau, doubl
   ya.tau = tau;
   ya.part = part;
   ya.nfield = 9;
-  if (timed(f, 2, stream, [&] { return eles::launch_y(ya, true, f->ygemm, stream); }) != hipSuccess)
+  const bool staged = f->ys_ok && f->ygemm == ELES_YGEMM_FP32;
+  if (timed(f, 2, stream, [&] {
+        return staged ? eles::launch_ys(ya, f->ys, stream) : eles::launch_y(ya, true, f->ygemm, stream);
+      }) != hipSuccess)
     return ELES_EHIP;
   if (stats) {
-    const int nparts = eles::y_parts(f->d.nx, f->n16);
     const double inv = 1.0 / ((double)f->d.nx * f->d.nz);
+    const int nparts = sgs_parts(f, staged);
     if (timed(f, 3, stream, [&] { return eles::launch_stats(part, stats, f->d.ny, nparts, inv, stream); }) !=
         hipSuccess)
       return ELES_EHIP;

@@ -69,7 +69,7 @@ struct YArgs {
   float *ubar, *tau;      // sgs outputs, planar [3][nx][ny][nz] / [6][...]
   float *out;             // plain outputs, element (x, i, z) of field f at
   size_t out_fs, out_xs, out_ks;   // out[f*out_fs + x*out_xs + i*out_ks + z]
-  double *part;           // sgs plane partials [9][ny][y_parts()] or null
+  double *part;           // sgs plane partials [9][ny][parts] or null
   const float *a32[4];
   const uint16_t *ahi[4], *alo[4];
   const int *rowband;
@@ -80,6 +80,30 @@ struct YArgs {
 hipError_t launch_y(const YArgs &a, bool sgs, int prec, hipStream_t s);
 // Number of plane partials per (quantity, row) the stress y pass writes.
 inline int y_parts(int nx, int n16) { return nx * ((n16 + kYWaves - 1) / kYWaves); }
+
+// Stress y pass staged through LDS, k_ys.hip: persistent blocks, each
+// keeping one group of consecutive 16-row output tiles (band rows
+// [kb, kb + nrow)) and walking the (x, 16-column strip) pencils.
+constexpr int kYsRow = 9 * kYTileN + 4;   // floats per staged row (9 fields x 16, + bank pad)
+constexpr int kYsMaxTiles = 3;            // tiles per group
+constexpr int kYsMaxGroups = 32;
+constexpr int kYsMaxChunks = 384;         // chunk table entries over all groups
+constexpr int kYsMaxGroupChunks = 24;     // chunks of one group (the walk is unrolled to this)
+constexpr size_t kYsLdsMax = 163840;
+struct YsPlan {
+  int nblk;                               // persistent grid: a multiple of ngroup
+  int ngroup;
+  int lds_rows;                           // staged rows allocated per block
+  int max_chunks;                         // most 16-column chunks of one group
+  int tile0[kYsMaxGroups], ntile[kYsMaxGroups], kb[kYsMaxGroups], nrow[kYsMaxGroups];
+  int chunk0[kYsMaxGroups], nchunk[kYsMaxGroups];
+  // per chunk of a group, in walk order: first column | tile in group << 16
+  // | (last chunk of its tile) << 24
+  int chunk[kYsMaxChunks];
+};
+size_t ys_lds_bytes(const YsPlan &p);
+int ys_grid(const YsPlan &p, int nz, int npencils);   // 0 if the kernel cannot run
+hipError_t launch_ys(const YArgs &a, const YsPlan &p, hipStream_t s);
 hipError_t launch_stats(const double *part, double *stats, int ny, int nparts,
                         double inv_count, hipStream_t s);
 

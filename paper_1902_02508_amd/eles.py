@@ -41,6 +41,7 @@ class StateLayout(ctypes.Structure):
         ("off_wx64", ctypes.c_size_t), ("off_wz64", ctypes.c_size_t),
         ("off_y64", ctypes.c_size_t), ("off_shift", ctypes.c_size_t),
         ("state_bytes", ctypes.c_size_t),
+        ("y_groups", ctypes.c_int32), ("y_blocks", ctypes.c_int32),
     ]
 
 

@@ -101,10 +101,15 @@ def _sgs_case(E, cfg, seed, tail=0.0, mode="fp32"):
     return y, u, _host(ub), _host(tau), _host(st), f
 
 
+# (label, base config, overrides, seed, y-pass route): "staged" is the
+# LDS-staged persistent kernel, "direct" the one it falls back to when a
+# row group does not fit in LDS (here: a y filter as wide as the channel).
 SGS_CASES = [
-    ("tiny", "tiny", dict(), 0),
-    ("odd", "tiny", dict(nx=10, nz=13, ny=21, ykind="tanh", stretch=2.0), 1),
-    ("ragged192", "dns192", dict(nx=27, nz=70, ny=37), 2),
+    ("tiny", "tiny", dict(), 0, "staged"),
+    ("odd", "tiny", dict(nx=10, nz=13, ny=21, ykind="tanh", stretch=2.0), 1, "staged"),
+    ("ragged192", "dns192", dict(nx=27, nz=70, ny=37), 2, "staged"),
+    ("strip36", "dns192", dict(nx=20, nz=36, ny=65), 3, "staged"),
+    ("wide_y", "tiny", dict(nx=12, nz=16, ny=193, delta_y=1.0), 4, "direct"),
 ]
 
 
@@ -130,10 +135,14 @@ def fp32_tolerances(u, ops, y):
     return tol
 
 
-@pytest.mark.parametrize("label,base,over,seed", SGS_CASES)
-def test_sgs_stress_matches_oracle(E, label, base, over, seed):
+@pytest.mark.parametrize("label,base,over,seed,route", SGS_CASES)
+def test_sgs_stress_matches_oracle(E, label, base, over, seed, route):
     cfg = synth.config(base, **over)
-    y, u, ub, tau, st, _ = _sgs_case(E, cfg, seed)
+    y, u, ub, tau, st, f = _sgs_case(E, cfg, seed)
+    groups = f.layout.y_groups
+    assert (groups > 0) == (route == "staged"), (label, groups)
+    if groups:
+        assert f.layout.y_blocks % groups == 0 and f.layout.y_blocks >= groups
     ops = R.Operators.from_config(cfg)
     rub, rtau = R.sgs_stress(u.astype(np.float64), ops)
     tol = fp32_tolerances(u, ops, y)
