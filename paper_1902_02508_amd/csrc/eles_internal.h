@@ -10,7 +10,7 @@ namespace eles {
 
 constexpr int kXzThreads = 256;   // x/z pass block size (one column per thread)
 constexpr int kXzTileX = 8;       // x outputs per x/z tile
-constexpr int kXzRunZ = 8;        // z outputs per thread in the z stage
+constexpr int kXzRunZ = 4;        // z outputs per item of the z stage (one 16-byte store)
 constexpr int kXzRowPad = 16;     // LDS row padding of the x-filtered tile
 constexpr int kMaxHalfX = 128;    // largest x stencil half-width
 constexpr int kMaxHalfZ = 120;    // largest z stencil half-width: 2m + 8 <= 256
@@ -28,8 +28,11 @@ __device__ inline int xcd_remap(int b, int nb) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
-// Length of a zero-padded FP32 tap array of half-width m.
-__host__ __device__ inline int tap_pad_len(int m) { return 2 * m + 2 * kXzTileX + 8; }
+// Length of a zero-padded FP32 tap array of half-width m: entry e holds the
+// tap of offset e - (kXzTileX - 1) - m, zero outside [kXzTileX - 1,
+// kXzTileX - 1 + 2m]; the tail covers the widest window a stencil group
+// reads (the z stage fetches 40 entries at a time).
+__host__ __device__ inline int tap_pad_len(int m) { return 2 * m + 2 * kXzTileX + 40; }
 
 // Operators resident in the caller's state buffer.
 struct OpsView {

@@ -8,13 +8,16 @@
 // eight x-filtered outputs per field in registers. In the stress mode the
 // fields are u1' = u1 - m(y), u2, u3 and their six products, so the raw
 // velocity is read once and the products are never stored. The x-filtered
-// strip goes to LDS. Stage Z: each thread takes runs of eight z outputs of
-// one (field, x) row and applies the z stencil from LDS, writing coalesced
-// rows back to HBM. The nine outputs are interleaved by row, [x][y][f][z],
+// strip goes to LDS. Stage Z: each thread takes runs of four z outputs of
+// one (field, x) row and applies the z stencil from LDS, writing each run
+// as one 16-byte store, so four neighbouring lanes fill a whole 64-byte
+// segment (runs of eight as eight 4-byte stores cost four times the L2
+// write requests). The nine outputs are interleaved by row, [x][y][f][z],
 // so the y pass finds all fields of one (x, y) row side by side.
 //
 // Taps are read through uniform (scalar) loads from zero-padded tap arrays,
-// so the per-output loops carry no bounds tests.
+// so the per-output loops carry no bounds tests; each group of four inputs
+// fetches its eleven taps at once.
 #include "eles_internal.h"
 
 namespace eles {
@@ -22,6 +25,8 @@ namespace {
 
 constexpr int XT = kXzTileX;
 constexpr int RZ = kXzRunZ;
+constexpr int kZGroups = 8;  // z-stage input groups fetched at once
+static_assert(RZ == 4, "the z stage stores runs of four");
 
 __device__ inline int wrap(int i, int n) {
   i %= n;
@@ -74,40 +79,83 @@ __device__ inline bool reach(int r, int o, int m2) {
   return o <= r && r - o <= m2;
 }
 
+// The taps a group of four inputs b..b+3 and eight outputs uses: entries
+// b .. b+10 of the padded tap array (input b+k reaches output o through
+// entry b + k + 7 - o). b is a multiple of 4, so the window is three
+// aligned 16-byte uniform loads, one wait per group instead of one per tap.
+__device__ inline void tap_window(const float *__restrict__ w, int b, float (&t)[12]) {
+  const float4 *p = reinterpret_cast<const float4 *>(w + b);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float4 q = p[i];
+    t[4 * i] = q.x;
+    t[4 * i + 1] = q.y;
+    t[4 * i + 2] = q.z;
+    t[4 * i + 3] = q.w;
+  }
+}
+
 template <bool SGS, int MODE, int R0>
 __device__ inline void x_group(float (&acc)[Fields<SGS>::NF][XT], const float (&cur)[4][3], float ms,
                                const float *__restrict__ wx, int r0, int m2) {
   constexpr int NF = Fields<SGS>::NF;
+  const int rb = MODE == G_HEAD ? R0 : r0;
+  float tw[12];
+  tap_window(wx, rb, tw);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const float c3[3] = {cur[k][0] - ms, cur[k][1], cur[k][2]};
     float v[NF];
     Fields<SGS>::form(c3, v);
-    const int r = (MODE == G_HEAD ? R0 : r0) + k;
-    const float *w = wx + (r + XT - 1);
+    const int r = rb + k;
 #pragma unroll
     for (int o = 0; o < XT; ++o) {
       if (!reach<MODE>(r, o, m2)) continue;
-      const float wt = w[-o];
+      const float wt = tw[k + XT - 1 - o];
 #pragma unroll
       for (int f = 0; f < NF; ++f) acc[f][o] = fmaf(wt, v[f], acc[f][o]);
     }
   }
 }
 
-template <int MODE, int T0>
-__device__ inline void z_group(float (&acc)[RZ], const float *src, const float *__restrict__ wz, int t4, int m2) {
-  const int tb = MODE == G_HEAD ? T0 : t4;
-  const float4 v = *reinterpret_cast<const float4 *>(src + tb);
-  const float vv[4] = {v.x, v.y, v.z, v.w};
+// z stencil of one run of RZ = 4 outputs from its LDS row, kZGroups groups
+// of four inputs at a time: the chunk's LDS values (one 16-byte read per
+// group) and its 4 kZGroups + 8 taps (uniform 16-byte loads) are all
+// requested before the first product, so a chunk waits once. Input t
+// reaches output q through padded tap entry t + XT - 1 - q; entries past
+// the stencil are zero, which also covers the first group's missing pairs
+// and the groups past the row's end (they read a valid LDS address and
+// meet only zero taps: their entries start at 4 ngz + XT - 4 > XT - 1 + 2m).
+__device__ inline void z_run(float (&acc)[RZ], const float *src, const float *__restrict__ wz, int ngz) {
+  for (int g0 = 0; g0 < ngz; g0 += kZGroups) {
+    float4 v[kZGroups];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int t = tb + k;
-    const float *w = wz + (t + RZ - 1);
+    for (int j = 0; j < kZGroups; ++j) {
+      const int g = g0 + j < ngz ? g0 + j : ngz - 1;
+      v[j] = *reinterpret_cast<const float4 *>(src + 4 * g);
+    }
+    float tw[4 * kZGroups + 8];
+    {
+      const float4 *p = reinterpret_cast<const float4 *>(wz + 4 * g0 + XT - RZ);
 #pragma unroll
-    for (int q = 0; q < RZ; ++q) {
-      if (!reach<MODE>(t, q, m2)) continue;
-      acc[q] = fmaf(w[-q], vv[k], acc[q]);
+      for (int i = 0; i < kZGroups + 2; ++i) {
+        const float4 q = p[i];
+        tw[4 * i] = q.x;
+        tw[4 * i + 1] = q.y;
+        tw[4 * i + 2] = q.z;
+        tw[4 * i + 3] = q.w;
+      }
+    }
+    // every request above is issued before the first product (the fence
+    // keeps the compiler from sinking the LDS reads to their uses)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < kZGroups; ++j) {
+      const float vv[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < RZ; ++q) acc[q] = fmaf(tw[4 * j + k + RZ - 1 - q], vv[k], acc[q]);
     }
   }
 }
@@ -216,27 +264,28 @@ k_xz(XzArgs a, const float *__restrict__ gin, float *__restrict__ gout,
     }
     __syncthreads();
     const int items = nfg * XT * nch;
+    const int ngz = (zrows + 3) / 4;
     for (int it = tid; it < items; it += kXzThreads) {
       const int c = it % nch;
       const int row = it / nch;
       const int f = f0 + row / XT, o = row % XT;
       const int xg = x0 + o;
       if (xg >= a.nx || f >= (SGS ? NF : a.ncomp)) continue;
-      const float *src = tx + row * zs + c * RZ;
       float zacc[RZ];
 #pragma unroll
       for (int q = 0; q < RZ; ++q) zacc[q] = 0.0f;
-      if (mz2 >= RZ) {
-        z_group<G_HEAD, 0>(zacc, src, wz, 0, mz2);
-        z_group<G_HEAD, 4>(zacc, src, wz, 4, mz2);
-        for (int t4 = RZ; t4 < zrows; t4 += 4) z_group<G_FULL, 0>(zacc, src, wz, t4, mz2);
+      z_run(zacc, tx + row * zs + c * RZ, wz, ngz);
+      // a run of RZ = 4 outputs leaves as one 16-byte store where it can
+      // (four neighbouring lanes then fill a whole 64-byte segment)
+      const int zl = c * RZ;
+      float *dst = gout + (((size_t)xg * a.ny + y) * a.out_nf + f) * a.nz + z0 + zl;
+      if ((a.nz & 3) == 0 && zl + 3 < a.zt && z0 + zl + 3 < a.nz) {
+        *reinterpret_cast<float4 *>(dst) = make_float4(zacc[0], zacc[1], zacc[2], zacc[3]);
       } else {
-        for (int t4 = 0; t4 < zrows; t4 += 4) z_group<G_ANY, 0>(zacc, src, wz, t4, mz2);
-      }
-      float *dst = gout + (((size_t)xg * a.ny + y) * a.out_nf + f) * a.nz + z0 + c * RZ;
 #pragma unroll
-      for (int q = 0; q < RZ; ++q)
-        if (c * RZ + q < a.zt && z0 + c * RZ + q < a.nz) dst[q] = zacc[q];
+        for (int q = 0; q < RZ; ++q)
+          if (zl + q < a.zt && z0 + zl + q < a.nz) dst[q] = zacc[q];
+      }
     }
   }
 }
