@@ -244,6 +244,34 @@ def sgs_stress_shifted(u: np.ndarray, ops: Operators, m: np.ndarray):
     return ubar, np.stack([t11, t12, t13, t22, t23, t33])
 
 
+# ------------------------------------------------- outputs on selected wall-normal rows
+
+def filt_rows(f: np.ndarray, parity: int, ops: Operators, rows) -> np.ndarray:
+    """F(f)[:, rows, :]: the y operator's selected rows applied over the
+    y nodes they reach, then the x and z filters ([nx, len(rows), nz])."""
+    rows = np.asarray(rows)
+    W = ops.W(parity)[rows]
+    band = np.nonzero(np.any(W != 0.0, axis=0))[0]
+    g = np.asarray(f[:, band, :], dtype=np.float64)
+    return filt_xz(apply_y(g, W[:, band]), ops)
+
+
+def sgs_rows(u: np.ndarray, ops: Operators, rows):
+    """ubar [3, nx, R, nz] and tau [6, nx, R, nz] on the selected rows: the
+    four steps of Sec. 2.1 with every filter evaluated only where needed."""
+    rows = np.asarray(rows)
+    ub = np.stack([filt_rows(u[i], PARITY[i], ops, rows) for i in range(3)])
+    tau = np.empty((6,) + ub.shape[1:])
+    for k, (i, j) in enumerate(PAIRS):
+        s = PARITY[i] * PARITY[j]
+        W = ops.W(s)[rows]
+        band = np.nonzero(np.any(W != 0.0, axis=0))[0]
+        prod = np.asarray(u[i][:, band, :], dtype=np.float64) * u[j][:, band, :]
+        tau[k] = filt_xz(apply_y(prod, W[:, band]), ops) - ub[i] * ub[j]
+        del prod
+    return ub, tau
+
+
 # ------------------------------------------------- outputs at sampled points
 
 def taps(n: int, length: float, delta: float, tail_tol: float = 0.0) -> Tuple[np.ndarray, np.ndarray]:

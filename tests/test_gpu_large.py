@@ -1,0 +1,84 @@
+"""Parity at the large channel shapes on selected wall-normal rows.
+
+The oracle evaluates the four steps of Sec. 2.1 only on the listed rows
+(oracle.filter_ref.sgs_rows, pinned against the full oracle on the CPU), so
+the 512 x 257 x 512 and 1024 x 385 x 768 grids are compared at full size:
+every x and z of the rows, with the walls, the near-wall band and the
+centre. The first test is the y-pass precision study (FP32 / BF16x3 / BF16
+operators on the matrix cores); the second runs the production shape in
+the launch configuration of the benchmark path (FP32, LDS-staged y pass).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import filter_ref as R
+from paper_1902_02508_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1902_02508_amd import eles
+    return eles
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b * b)))
+
+
+def _run(E, cfg, u, mode, tail, rows):
+    dev = torch.device("cuda", torch.cuda.current_device())
+    f = E.Filter.from_config(cfg, tail_tol=tail, ygemm=mode, device=dev)
+    du = torch.from_numpy(u).to(dev)
+    ub, tau, st = f.sgs_stress(du)
+    idx = torch.as_tensor(rows, device=dev)
+    gub = ub.index_select(2, idx).cpu().numpy()
+    gtau = tau.index_select(2, idx).cpu().numpy()
+    groups = f.layout.y_groups
+    del f, du, ub, tau, st
+    torch.cuda.empty_cache()
+    return gub, gtau, groups
+
+
+def test_dns512_rows_y_precision(E):
+    """512 x 257 x 512, 1e-8 tail, rows 0, 1, 4, 16, 64, 128, 192, 256:
+    FP32 within 2e-5 on every output, BF16x3 within 1e-4, BF16 within 5e-2
+    (relative L2 over the rows)."""
+    cfg = synth.config("dns512")
+    tail = 1e-8
+    y, u = synth.make_snapshot(cfg, 0)
+    rows = [0, 1, 4, 16, 64, 128, 192, 256]
+    ops = R.Operators.from_config(cfg, tail_tol=tail)
+    rub, rtau = R.sgs_rows(u, ops, rows)
+    limits = {"fp32": 2e-5, "bf16x3": 1e-4, "bf16": 5e-2}
+    for mode, lim in limits.items():
+        gub, gtau, groups = _run(E, cfg, u, mode, tail, rows)
+        errs = [_rel(gub[k], rub[k]) for k in range(3)] + [_rel(gtau[k], rtau[k]) for k in range(6)]
+        per_row = [max(_rel(gtau[k][:, r], rtau[k][:, r]) for k in range(6)) for r in range(len(rows))]
+        print(f"dns512 {mode}: max rel L2 {max(errs):.2e}; per output "
+              + " ".join(f"{e:.1e}" for e in errs) + "; worst tau per row "
+              + " ".join(f"{e:.1e}" for e in per_row), flush=True)
+        assert max(errs) < lim, (mode, errs)
+        if mode == "fp32":
+            assert groups > 0
+
+
+def test_dns1024_rows_production_shape(E):
+    """1024 x 385 x 768 at the 1e-8 tail, FP32 path (LDS-staged y pass), rows
+    at both walls, in the near-wall band and at the centre: every output
+    within 2e-5 relative L2."""
+    cfg = synth.config("dns1024")
+    tail = 1e-8
+    y, u = synth.make_snapshot(cfg, synth.SEEDS["dns1024"][0])
+    rows = [0, 1, 6, 48, 192, 336, 383, 384]
+    ops = R.Operators.from_config(cfg, tail_tol=tail)
+    rub, rtau = R.sgs_rows(u, ops, rows)
+    gub, gtau, groups = _run(E, cfg, u, "fp32", tail, rows)
+    assert groups > 0
+    errs = [_rel(gub[k], rub[k]) for k in range(3)] + [_rel(gtau[k], rtau[k]) for k in range(6)]
+    print("dns1024 fp32: per output " + " ".join(f"{e:.1e}" for e in errs), flush=True)
+    assert max(errs) < 2e-5, errs

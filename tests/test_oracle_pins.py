@@ -387,3 +387,19 @@ def test_pins_catch_planted_mistakes(monkeypatch):
     assert fold_error((good[0].T, good[1].T)) > 1e-6
     # swapped parities
     assert fold_error((good[1], good[0])) > 1e-6
+
+
+def test_row_restricted_outputs_equal_full_oracle():
+    """sgs_rows (the y operator's selected rows over the nodes they reach)
+    agrees with the full oracle restricted to those rows, walls included."""
+    for base, over in (("tiny", {}), ("dns192", dict(nx=24, nz=20, ny=37))):
+        cfg = synth.config(base, **over)
+        y, u = synth.make_snapshot(cfg, 3)
+        ops = R.Operators.from_config(cfg)
+        ub, tau = R.sgs_stress(u.astype(np.float64), ops)
+        rows = [0, 1, cfg.ny // 2, cfg.ny - 2, cfg.ny - 1]
+        rub, rtau = R.sgs_rows(u, ops, rows)
+        scale_u = np.abs(ub).max()
+        scale_t = np.abs(tau).max()
+        assert np.max(np.abs(rub - ub[:, :, rows, :])) < 1e-13 * scale_u
+        assert np.max(np.abs(rtau - tau[:, :, rows, :])) < 1e-12 * scale_t
