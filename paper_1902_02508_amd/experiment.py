@@ -1,6 +1,6 @@
 """The learned-closure experiment: train on exact stresses, judge against them.
 
-    python -m paper_1902_02508_amd.experiment [--train 32] [--heldout 4] [--steps 20000]
+    python -m paper_1902_02508_amd.experiment [--train 32] [--heldout 4] [--steps 20000] [--production 8]
 
 Training snapshots (seeded synthetic channel fields) go through the exact
 path (filtered velocity and tau_ij), their gradient features are built on
@@ -150,6 +150,81 @@ def time_paths(cl, f, cfg, dev, reps=20):
     return {"exact_points_per_s": exact, "closure_points_per_s": learned, "speedup": learned / exact}
 
 
+def production(cl, n_snap=8, tail=1e-8, workload="dns1024", log=print):
+    """Exact path vs closure inference at the production shape.
+
+    n_snap snapshots are staged in HBM first (host-to-device copies from
+    pinned buffers timed on their own); the exact path is timed over all of
+    them with the FP32 and the BF16x3 y pass, the closure's inference
+    (features from ubar + perceptron + plane means) over the same filtered
+    velocities, and each snapshot's closure <tau_12>(y) is compared with the
+    exact FP64 plane statistics.
+    """
+    dev = torch.device("cuda", torch.cuda.current_device())
+    cfg = synth.config(workload)
+    y = synth.ygrid(cfg.ny, cfg.ykind, cfg.stretch)
+    seeds = synth.SEEDS[workload][:n_snap]
+    us, h2d_s, nbytes = [], 0.0, 0
+    for s in seeds:
+        _, u = synth.make_snapshot(cfg, s)
+        host = torch.from_numpy(u).pin_memory()
+        d = torch.empty(host.shape, dtype=host.dtype, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d.copy_(host, non_blocking=True)
+        torch.cuda.synchronize()
+        h2d_s += time.perf_counter() - t0
+        nbytes += host.numel() * 4
+        us.append(d)
+        del host, u
+        log(f"  staged snapshot {s} ({len(us)}/{len(seeds)})")
+    pts = cfg.points * len(us)
+    res = {"workload": f"channel {cfg.nx}x{cfg.ny}x{cfg.nz}", "snapshots": len(us),
+           "h2d_GBps": nbytes / h2d_s / 1e9}
+    shape = (cfg.nx, cfg.ny, cfg.nz)
+    tau = torch.empty((6,) + shape, dtype=torch.float32, device=dev)
+    for mode in ("fp32", "bf16x3"):
+        f = eles.Filter.from_config(cfg, tail_tol=tail, ygemm=mode, device=dev)
+        ub = torch.empty((3,) + shape, dtype=torch.float32, device=dev)
+        st = torch.empty((9, cfg.ny), dtype=torch.float64, device=dev)
+        f.sgs_stress(us[0], ub, tau, st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for u in us:
+            f.sgs_stress(u, ub, tau, st)
+        torch.cuda.synchronize()
+        res[f"exact_{mode}_points_per_s"] = pts / (time.perf_counter() - t0)
+        log(f"  exact {mode}: {res[f'exact_{mode}_points_per_s']:.3e} points/s")
+        del f, ub, st
+        torch.cuda.empty_cache()
+    f = eles.Filter.from_config(cfg, tail_tol=tail, device=dev)
+    ubs, stats = [], []
+    for u in us:
+        ub = torch.empty((3,) + shape, dtype=torch.float32, device=dev)
+        st = torch.empty((9, cfg.ny), dtype=torch.float64, device=dev)
+        f.sgs_stress(u, ub, tau, st)
+        ubs.append(ub)
+        stats.append(st)
+    del tau
+    torch.cuda.empty_cache()
+    pred = torch.empty((6,) + shape, dtype=torch.float32, device=dev)
+    pst = [torch.empty((6, cfg.ny), dtype=torch.float64, device=dev) for _ in ubs]
+    cl.infer(f, ubs[0], pred, pst[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ub, ps in zip(ubs, pst):
+        cl.infer(f, ub, pred, ps)
+    torch.cuda.synchronize()
+    res["closure_points_per_s"] = pts / (time.perf_counter() - t0)
+    errs = [profile_error(ps[1].cpu().numpy(), st[4].cpu().numpy(), y) for ps, st in zip(pst, stats)]
+    res["tau12_profile_error"] = float(np.mean(errs))
+    res["tau12_profile_error_max"] = float(np.max(errs))
+    res["speedup_vs_fp32"] = res["closure_points_per_s"] / res["exact_fp32_points_per_s"]
+    res["speedup_vs_bf16x3"] = res["closure_points_per_s"] / res["exact_bf16x3_points_per_s"]
+    log(f"  closure: {res['closure_points_per_s']:.3e} points/s, <tau12> profile error {res['tau12_profile_error']:.3f}")
+    return res
+
+
 def run(n_train=32, n_heldout=4, steps=20000, batch=65536, lr=1e-3, seed=1, workload="dns192",
         tail=1e-8, log=print):
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -202,9 +277,15 @@ def main(argv=None):
     p.add_argument("--batch", type=int, default=65536)
     p.add_argument("--lr", type=float, default=1e-3)
     p.add_argument("--seed", type=int, default=1)
+    p.add_argument("--production", type=int, default=0, metavar="N",
+                   help="also time exact path vs closure on N staged 1024x385x768 snapshots")
     a = p.parse_args(argv)
-    res, _, _ = run(a.train, a.heldout, a.steps, a.batch, a.lr, a.seed,
-                    log=lambda m: print(m, file=sys.stderr, flush=True))
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    res, cl, f = run(a.train, a.heldout, a.steps, a.batch, a.lr, a.seed, log=log)
+    if a.production > 0:
+        del f
+        torch.cuda.empty_cache()
+        res["production"] = production(cl, a.production, log=log)
     print(json.dumps(res), flush=True)
 
 
