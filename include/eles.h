@@ -98,6 +98,9 @@ typedef struct {
                                   pass; 0 when this grid uses the direct
                                   y pass instead                              */
   int32_t y_blocks;            /* persistent blocks of the staged y pass      */
+  int32_t xz_waves;            /* waves of the matrix-core stress x/z pass;
+                                  0 when this grid uses the vector-unit
+                                  x/z pass instead                            */
 } eles_state_layout;
 
 /* Human-readable name of a status code. Never NULL. */
@@ -118,6 +121,15 @@ int32_t filter_setup(const eles_filter_desc *desc, void *state, size_t state_byt
 
 /* Choose the y-pass arithmetic (eles_ygemm) for later calls. */
 int32_t filter_set_ygemm(eles_filter f, int32_t ygemm);
+
+/* Choose how later sgs_stress calls evaluate the periodic x and z parts of
+ * the filter (Sec. 2.1, eq. (2)) on the nine fields: 1 = on the matrix cores
+ * (the default wherever that kernel covers the grid: x and z stencil
+ * half-widths up to 16, nx >= 4), 0 = on the vector units. Both give the
+ * same result up to FP32 rounding order. Errors: EINVAL (null handle, value
+ * other than 0 or 1), ENOTSUP (1 asked for a grid the matrix-core kernel
+ * does not cover; the setting is left unchanged). */
+int32_t filter_set_xz(eles_filter f, int32_t matrix_cores);
 
 /* Operator layout of the handle's state. */
 int32_t filter_state_layout(eles_filter f, eles_state_layout *out);

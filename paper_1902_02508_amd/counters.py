@@ -28,6 +28,7 @@ CSRC = os.path.join(HERE, "csrc")
 # kernel symbol fragment -> (short name, sources it is compiled from)
 KERNELS = {
     "k_xz": ("k_xz", ["k_xz.hip", "eles_internal.h"]),
+    "k_xzm": ("k_xzm", ["k_xzm.hip", "eles_internal.h"]),
     "k_ys": ("k_ys", ["k_ys.hip", "eles_internal.h"]),
 }
 

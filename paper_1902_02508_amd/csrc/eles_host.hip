@@ -22,6 +22,9 @@ struct eles_filter_s {
   size_t npts;
   bool ys_ok;          // the staged stress y pass fits this grid
   eles::YsPlan ys;
+  bool xzm_ok;         // the matrix-core stress x/z pass covers this grid
+  bool xzm_on = true;  // ... and is selected
+  eles::XzmPlan xzm;
   // per-pass event timing
   int prof_max = 0, prof_calls = 0;
   std::vector<hipEvent_t> ev;   // [call][pass][start, stop]
@@ -406,6 +409,8 @@ int32_t filter_setup(const eles_filter_desc *desc, void *state, size_t state_byt
   }
   L.y_groups = f->ys_ok ? f->ys.ngroup : 0;
   L.y_blocks = f->ys_ok ? f->ys.nblk : 0;
+  f->xzm_ok = eles::xzm_plan(desc->nx, desc->ny, desc->nz, p.mx, p.mz, &f->xzm);
+  L.xz_waves = f->xzm_ok ? f->xzm.nblk * eles::kXzmWaves : 0;
   *out = f;
   return ELES_OK;
 }
@@ -413,6 +418,13 @@ int32_t filter_setup(const eles_filter_desc *desc, void *state, size_t state_byt
 int32_t filter_set_ygemm(eles_filter f, int32_t ygemm) {
   if (!f || ygemm < ELES_YGEMM_FP32 || ygemm > ELES_YGEMM_BF16X3) return ELES_EINVAL;
   f->ygemm = ygemm;
+  return ELES_OK;
+}
+
+int32_t filter_set_xz(eles_filter f, int32_t matrix_cores) {
+  if (!f || (matrix_cores != 0 && matrix_cores != 1)) return ELES_EINVAL;
+  if (matrix_cores && !f->xzm_ok) return ELES_ENOTSUP;
+  f->xzm_on = matrix_cores == 1;
   return ELES_OK;
 }
 
@@ -496,7 +508,10 @@ int32_t sgs_stress(eles_filter f, const float *u, float *ubar, float *tau, doubl
   xa.out_nf = 9;
   xa.mshift = f->v.prof32;
   xa.ncomp = 3;
-  if (timed(f, 1, stream, [&] { return eles::launch_xz(xa, true, stream); }) != hipSuccess) return ELES_EHIP;
+  if (timed(f, 1, stream, [&] {
+        return f->xzm_ok && f->xzm_on ? eles::launch_xzm(xa, f->xzm, stream) : eles::launch_xz(xa, true, stream);
+      }) != hipSuccess)
+    return ELES_EHIP;
   eles::YArgs ya = y_args(f);
   ya.in = X;
   ya.in_fs = f->d.nz;

@@ -63,6 +63,24 @@ struct XzArgs {
 hipError_t launch_xz(const XzArgs &a, bool sgs, hipStream_t s);
 int xz_tile_z(int nz, int mz);
 
+// Stress x/z pass on the matrix cores, k_xzm.hip: persistent waves, each
+// taking an equal contiguous range of the 16 x 16 output tiles of all
+// (y, 16-row x tile) rows.
+constexpr int kXzmWaves = 4;   // waves per block of the matrix-core x/z pass
+struct XzmPlan {
+  int ks;     // x stencil steps of four input rows (covers 16 + 2 mx rows)
+  int h;      // z chunks on each side of a tile (covers mz)
+  int vec;    // nz % 4 == 0: 16-byte stores
+  int nxt;    // 16-row x tiles
+  int nct;    // 16-column z tiles
+  int nrow;   // rows: ny * nxt
+  int nblk;   // blocks of kXzmWaves waves
+};
+// False when the grid is outside what the kernel covers (the VALU kernel
+// k_xz then runs instead).
+bool xzm_plan(int nx, int ny, int nz, int mx, int mz, XzmPlan *p);
+hipError_t launch_xzm(const XzArgs &a, const XzmPlan &p, hipStream_t s);
+
 // y pass, k_y.hip.
 struct YArgs {
   // element (x, k, z) of input field f sits at in[f*in_fs + x*in_xs + k*in_ks + z];

@@ -42,6 +42,7 @@ class StateLayout(ctypes.Structure):
         ("off_y64", ctypes.c_size_t), ("off_shift", ctypes.c_size_t),
         ("state_bytes", ctypes.c_size_t),
         ("y_groups", ctypes.c_int32), ("y_blocks", ctypes.c_int32),
+        ("xz_waves", ctypes.c_int32),
     ]
 
 
@@ -57,6 +58,7 @@ _SIG = {
     "filter_state_bytes": (_S, [ctypes.POINTER(FilterDesc)]),
     "filter_setup": (_I, [ctypes.POINTER(FilterDesc), _P, _S, _P, ctypes.POINTER(_P)]),
     "filter_set_ygemm": (_I, [_P, _I]),
+    "filter_set_xz": (_I, [_P, _I]),
     "filter_state_layout": (_I, [_P, ctypes.POINTER(StateLayout)]),
     "filter_workspace_bytes": (_S, [_P, _I]),
     "sgs_workspace_bytes": (_S, [_P]),
@@ -127,6 +129,10 @@ def filter_setup(desc, state_ptr, state_bytes, stream) -> _P:
 
 def filter_set_ygemm(h, ygemm: int):
     _check(lib.filter_set_ygemm(h, ygemm), "filter_set_ygemm")
+
+
+def filter_set_xz(h, matrix_cores: int):
+    _check(lib.filter_set_xz(h, matrix_cores), "filter_set_xz")
 
 
 def filter_state_layout(h) -> StateLayout:
@@ -226,6 +232,9 @@ class Filter:
 
     def set_ygemm(self, ygemm):
         filter_set_ygemm(self.h, YGEMM[ygemm] if isinstance(ygemm, str) else int(ygemm))
+
+    def set_xz(self, matrix_cores: bool):
+        filter_set_xz(self.h, 1 if matrix_cores else 0)
 
     def _workspace(self, nbytes):
         if self._ws.numel() < nbytes:

@@ -94,9 +94,11 @@ def test_filter_fields_match_oracle(E, name, over, mode, tol):
         assert err < tol, (k, err)
 
 
-def _sgs_case(E, cfg, seed, tail=0.0, mode="fp32"):
+def _sgs_case(E, cfg, seed, tail=0.0, mode="fp32", xz=None):
     y, u = synth.make_snapshot(cfg, seed)
     f = E.Filter.from_config(cfg, tail_tol=tail, ygemm=mode)
+    if xz is not None:
+        f.set_xz(xz == "matrix")
     ub, tau, st = f.sgs_stress(_dev(u))
     return y, u, _host(ub), _host(tau), _host(st), f
 
@@ -136,14 +138,21 @@ def fp32_tolerances(u, ops, y):
 
 
 @pytest.mark.parametrize("label,base,over,seed,route", SGS_CASES)
-def test_sgs_stress_matches_oracle(E, label, base, over, seed, route):
+@pytest.mark.parametrize("xz", ["matrix", "vector"])
+def test_sgs_stress_matches_oracle(E, label, base, over, seed, route, xz):
+    """Both x/z routes: the matrix-core kernel (run with the 1e-8 tail cut,
+    which brings every case's stencils within its half-width limit) and the
+    vector-unit kernel (full kernel)."""
     cfg = synth.config(base, **over)
-    y, u, ub, tau, st, f = _sgs_case(E, cfg, seed)
+    tail = 1e-8 if xz == "matrix" else 0.0
+    y, u, ub, tau, st, f = _sgs_case(E, cfg, seed, tail, xz=xz)
     groups = f.layout.y_groups
     assert (groups > 0) == (route == "staged"), (label, groups)
     if groups:
         assert f.layout.y_blocks % groups == 0 and f.layout.y_blocks >= groups
-    ops = R.Operators.from_config(cfg)
+    if xz == "matrix":
+        assert f.layout.xz_waves > 0, label
+    ops = R.Operators.from_config(cfg, tail_tol=tail)
     rub, rtau = R.sgs_stress(u.astype(np.float64), ops)
     tol = fp32_tolerances(u, ops, y)
     for k in range(3):
@@ -167,14 +176,17 @@ def test_sgs_stress_matches_oracle(E, label, base, over, seed, route):
 
 def test_sgs_dns192_full_size(E):
     """The 192 x 129 x 192 channel at its own widths, FP32 path, seeds 0-1,
-    with the full kernel and with the 1e-8 tail cut the benchmark uses."""
+    with the full kernel and with the 1e-8 tail cut the benchmark uses (both
+    x/z routes)."""
     cfg = synth.config("dns192")
     ops = R.Operators.from_config(cfg)
-    for seed, tail in ((0, 0.0), (1, 1e-8)):
-        y, u, ub, tau, st, _ = _sgs_case(E, cfg, seed, tail)
+    for seed, tail, xz in ((0, 0.0, None), (1, 1e-8, "matrix"), (1, 1e-8, "vector")):
+        y, u, ub, tau, st, f = _sgs_case(E, cfg, seed, tail, xz=xz)
+        if xz == "matrix":
+            assert f.layout.xz_waves > 0
         rub, rtau = R.sgs_stress(u.astype(np.float64), ops)
         errs = [_rel(ub[k], rub[k], y) for k in range(3)] + [_rel(tau[k], rtau[k], y) for k in range(6)]
-        print(f"seed {seed} tail {tail}: max rel L2 {max(errs):.2e}", flush=True)
+        print(f"seed {seed} tail {tail} x/z {xz}: max rel L2 {max(errs):.2e}", flush=True)
         assert max(errs) < 1e-5, errs
         ref12 = R.plane_mean(rtau[1])
         assert R.profile_error(st[4], ref12, y) < 1e-5
