@@ -63,17 +63,18 @@ struct XzArgs {
 hipError_t launch_xz(const XzArgs &a, bool sgs, hipStream_t s);
 int xz_tile_z(int nz, int mz);
 
-// Stress x/z pass on the matrix cores, k_xzm.hip: persistent waves, each
-// taking an equal contiguous range of the 16 x 16 output tiles of all
-// (y, 16-row x tile) rows.
+// Stress x/z pass on the matrix cores, k_xzm.hip: persistent blocks, each
+// taking an equal contiguous range of the z tiles of all (y, x group) rows;
+// the waves of a block take the group's neighbouring 16-row x tiles.
 constexpr int kXzmWaves = 4;   // waves per block of the matrix-core x/z pass
 struct XzmPlan {
   int ks;     // x stencil steps of four input rows (covers 16 + 2 mx rows)
   int h;      // z chunks on each side of a tile (covers mz)
   int vec;    // nz % 4 == 0: 16-byte stores
   int nxt;    // 16-row x tiles
+  int nxg;    // groups of kXzmWaves x tiles (one per wave of a block)
   int nct;    // 16-column z tiles
-  int nrow;   // rows: ny * nxt
+  int nrow;   // rows: ny * nxg
   int nblk;   // blocks of kXzmWaves waves
 };
 // False when the grid is outside what the kernel covers (the VALU kernel

@@ -25,13 +25,19 @@
 // z stencil
 //     Y[z_out][x] = sum over z_in of tz(z_in - z_out) X[z_in][x]
 // for four consecutive inputs. The x-filtered chunks feed the z product
-// from registers, with no exchange. The wave keeps the 2H + 1 chunks that
-// one z tile reads (H = ceil(mz / 16)) in a ring of register slots; the
-// chunk loop is unrolled by the ring length, so every slot is static.
+// from registers, with no exchange. The z stencil half-width is at most 16,
+// so a z tile reads its own chunk and one on each side.
 //
-// Loads: while step s of a chunk forms its products, the velocities of
-// step s of the next chunk are requested into the same registers, so each
-// load has a whole chunk of matrix work to arrive.
+// Chunks go in pairs: the two chunks of a pair are the two 64-byte halves
+// of the same 128-byte lines, requested together, so each line is fetched
+// once while both halves are wanted. The wave keeps four x-filtered chunks
+// in a ring of register slots (the pair just filtered and the one before);
+// after each pair it filters the two z tiles that became complete. The pair
+// loop is unrolled by two, so every slot is static.
+//
+// Loads: while step s of a pair forms its products, the velocities of step
+// s of the next pair are requested into the same registers, so each load
+// has a whole pair of matrix work to arrive.
 //
 // Each lane of a finished z tile holds four consecutive z outputs of one x,
 // stored as one 16-byte store into the row-interleaved [x][y][f][z] layout.
@@ -75,16 +81,18 @@ __device__ XZM_INLINE inline void static_for(F &&f) {
   }
 }
 
-template <int KS, int H, bool VEC>
-__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) k_xzm(XzArgs a, XzmPlan p) {
-  constexpr int NW = 2 * H + 1;   // chunks one z tile reads
+template <int KS, bool VEC>
+__global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1))) k_xzm(XzArgs a, XzmPlan p) {
+  constexpr int NR = 4;   // ring slots: two pairs of chunks
   const int lane = threadIdx.x & 63;
   const int i = lane & 15, j = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gw = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave;
-  const int nw = gridDim.x * kWaves;
+  // the block's range of (y, x group, z tile) positions; wave w takes x
+  // tile 4 g + w of group g, so the four waves walk the same z positions of
+  // neighbouring x tiles together and share their x-halo rows in cache
+  const int gb = xcd_remap(blockIdx.x, gridDim.x);
   const int total = p.nrow * p.nct;
-  const int start = (int)((long)gw * total / nw), end = (int)((long)(gw + 1) * total / nw);
+  const int start = (int)((long)gb * total / gridDim.x), end = (int)((long)(gb + 1) * total / gridDim.x);
   if (start >= end) return;
   const int nx = a.nx, nz = a.nz, mx = a.mx, mz = a.mz;
   const int plane = a.ny * nz;
@@ -94,13 +102,13 @@ __global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_e
   float bx[KS];
 #pragma unroll
   for (int s = 0; s < KS; ++s) bx[s] = tap(a.wx, mx, 4 * s + j - i - mx);
-  // z stencil, A operand of window chunk c (relative -H..H) and register r:
+  // z stencil, A operand of window chunk c (relative -1..1) and register r:
   // lane (output row i, k-slot j) holds tz(z_in - z_out), z_in = 16 c + 4 r + j
-  float az[NW][4];
+  float az[3][4];
 #pragma unroll
-  for (int c = 0; c < NW; ++c)
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) az[c][r] = tap(a.wz, mz, 16 * (c - H) + 4 * r + j - i);
+    for (int r = 0; r < 4; ++r) az[c][r] = tap(a.wz, mz, 16 * (c - 1) + 4 * r + j - i);
 
   // velocity components through buffer descriptors: 32-bit byte offsets,
   // no per-lane 64-bit addresses
@@ -113,62 +121,79 @@ __global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_e
   const int zrow = 4 * (i & 3) + (i >> 2);   // chunk column of A row i
   const unsigned row_bytes = (unsigned)a.ny * kNF * nz * 4;   // one x row of the output
 
-  // where the next chunk's velocities come from: first x row of this lane
-  // (wrapped), plane offset y nz, chunk index
+  // where the next pair's velocities come from: first x row of this lane
+  // (wrapped), plane offset y nz, first chunk of the pair
   int nxs, nyz, nk;
   auto target_row = [&](int y, int xt) XZM_INLINE {
     nxs = wrapi(16 * xt - mx + j, nx);
     nyz = y * nz;
   };
-  // element offset of the target chunk's first row; the modulo runs only
-  // for chunks that wrap around the periodic z direction
-  auto first = [&]() XZM_INLINE -> unsigned {
-    int zc = 16 * nk + zrow;
-    if (nk < 0 || 16 * nk + 16 > nz) zc = wrapi(zc, nz);
+  // element offset of chunk k's first row; the modulo runs only for chunks
+  // that wrap around the periodic z direction
+  auto first = [&](int k) XZM_INLINE -> unsigned {
+    int zc = 16 * k + zrow;
+    if (k < 0 || 16 * k + 16 > nz) zc = wrapi(zc, nz);
     return (unsigned)(nxs * plane + nyz + zc);
   };
-  float b[KS][3];
-  auto load_step = [&](int s, int &xi, unsigned &e) XZM_INLINE {
-    b[s][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(u0, e * 4, 0, 0));
-    b[s][1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(u1, e * 4, 0, 0));
-    b[s][2] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(u2, e * 4, 0, 0));
+  float b[2][KS][3];
+  auto load_step = [&](int s, int &xi, unsigned (&e)[2]) XZM_INLINE {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      b[h][s][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(u0, e[h] * 4, 0, 0));
+      b[h][s][1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(u1, e[h] * 4, 0, 0));
+      b[h][s][2] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(u2, e[h] * 4, 0, 0));
+    }
     // nx >= 4: one subtraction wraps; selects, not a branch
     xi += 4;
-    e += 4 * plane;
     const bool w = xi >= nx;
     xi = w ? xi - nx : xi;
-    e = w ? e - nx * plane : e;
+    const unsigned de = w ? 4 * plane - nx * plane : 4 * plane;
+    e[0] += de;
+    e[1] += de;
   };
 
-  f4 win[NW][kNF];
-  // x stencil of the chunk whose velocities are in b, into ring slot S,
-  // requesting the velocities of the current target into b step by step
+  f4 win[NR][kNF];
+  // x stencil of the pair whose velocities are in b, into ring slots S and
+  // S + 1, requesting the velocities of the target pair into b step by step
   auto xfilter = [&](auto slot, float ms) XZM_INLINE {
     constexpr int S = decltype(slot)::value;
     int xi = nxs;
-    unsigned e = first();
+    unsigned e[2] = {first(nk), first(nk + 1)};
 #pragma unroll
-    for (int f = 0; f < kNF; ++f) win[S][f] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int f = 0; f < kNF; ++f) {
+      win[S][f] = f4{0.f, 0.f, 0.f, 0.f};
+      win[S + 1][f] = f4{0.f, 0.f, 0.f, 0.f};
+    }
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const float v0 = b[s][0] - ms, v1 = b[s][1], v2 = b[s][2];
-      const float q[kNF] = {v0, v1, v2, v0 * v0, v0 * v1, v0 * v2, v1 * v1, v1 * v2, v2 * v2};
+      float q[2][kNF];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float v0 = b[h][s][0] - ms, v1 = b[h][s][1], v2 = b[h][s][2];
+        q[h][0] = v0, q[h][1] = v1, q[h][2] = v2;
+        q[h][3] = v0 * v0, q[h][4] = v0 * v1, q[h][5] = v0 * v2;
+        q[h][6] = v1 * v1, q[h][7] = v1 * v2, q[h][8] = v2 * v2;
+      }
       load_step(s, xi, e);
-      // keep this step's loads here, a whole chunk ahead of their use
+      // keep this step's loads here, a whole pair ahead of their use
       __builtin_amdgcn_sched_barrier(0);
       const float w = bx[s];
 #pragma unroll
-      for (int f = 0; f < kNF; ++f) win[S][f] = mma(q[f], w, win[S][f]);
+      for (int f = 0; f < kNF; ++f) {
+        win[S][f] = mma(q[0][f], w, win[S][f]);
+        win[S + 1][f] = mma(q[1][f], w, win[S + 1][f]);
+      }
     }
   };
-  // z stencil of tile t of row (y, x0) whose newest chunk sits in slot S.
-  // With nz % 4 == 0 every lane's four outputs are all inside or all outside
-  // the grid, and the stores go through a buffer descriptor whose range ends
-  // at the last x row: lanes past nx fall outside it, lanes past nz get an
-  // offset outside it, and the hardware drops both. Each tile then issues
-  // the same nine stores on every path, with no branch around them.
-  auto zfilter = [&](auto slot, int t, int y, int x0) XZM_INLINE {
-    constexpr int S = decltype(slot)::value;
+  // z stencil of tile t of row (y, x0) from ring slots S0, S0 + 1, S0 + 2
+  // (mod 4). With nz % 4 == 0 every lane's four outputs are all inside or
+  // all outside the grid, and the stores go through a buffer descriptor
+  // whose range ends at the last x row: lanes past nx fall outside it, lanes
+  // past nz get an offset outside it, and the hardware drops both. Each
+  // tile then issues the same nine stores on every path, with no branch
+  // around them.
+  auto zfilter = [&](auto slot, int t, int y, int x0, bool drop) XZM_INLINE {
+    constexpr int S0 = decltype(slot)::value;
     f4 acc[kNF];
 #pragma unroll
     for (int f = 0; f < kNF; ++f) acc[f] = f4{0.f, 0.f, 0.f, 0.f};
@@ -181,7 +206,7 @@ __global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_e
       const size_t rem = (size_t)(nx - x0) * row_bytes;
       rs = __builtin_amdgcn_make_buffer_rsrc(a.out + (size_t)x0 * (row_bytes / 4), 0,
                                              (int)(rem < 0x7fffffffu ? rem : 0x7fffffffu), kBufWord3);
-      off = zo < nz ? (unsigned)(i * row_bytes + (y * kNF * nz + zo) * 4) : 0x80000000u;
+      off = zo < nz && !drop ? (unsigned)(i * row_bytes + (y * kNF * nz + zo) * 4) : 0x80000000u;
     } else {
       dst = a.out + ((size_t)xo * a.ny + y) * (size_t)(kNF * nz) + zo;
     }
@@ -189,16 +214,16 @@ __global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_e
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
 #pragma unroll
-      for (int c = 0; c < NW; ++c)
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int f = 3 * g; f < 3 * g + 3; ++f) acc[f] = mma(az[c][r], win[(S + 1 + c) % NW][f][r], acc[f]);
+          for (int f = 3 * g; f < 3 * g + 3; ++f) acc[f] = mma(az[c][r], win[(S0 + c) % NR][f][r], acc[f]);
       if constexpr (VEC) {
 #pragma unroll
         for (int f = 3 * g; f < 3 * g + 3; ++f)
           __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, acc[f]), rs, off + f * nz * 4, 0, 0);
-      } else if (xo < nx) {
+      } else if (xo < nx && !drop) {
 #pragma unroll
         for (int f = 3 * g; f < 3 * g + 3; ++f)
 #pragma unroll
@@ -208,72 +233,74 @@ __global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_e
     }
   };
 
-  // the wave's range starts in row (y, xt) at tile ta; every later piece
-  // starts a new row at tile 0
-  int y, xt, ta;
+  // the range starts in row (y, x group xg) at tile ta; every later piece
+  // starts a new row at tile 0. A wave whose x tile 4 xg + w lies past the
+  // grid (last group when nxt % 4 != 0) runs the tile (4 xg + w) mod nxt
+  // with all its stores dropped: its loads stay in bounds and its memory
+  // operations keep their count.
+  int y, xg, ta;
   {
     const int row = start / p.nct;
     ta = start - row * p.nct;
-    y = row / p.nxt;
-    xt = row - y * p.nxt;
+    y = row / p.nxg;
+    xg = row - y * p.nxg;
   }
+  auto xtile = [&](int g) XZM_INLINE { return 4 * g + wave < p.nxt ? 4 * g + wave : (4 * g + wave) % p.nxt; };
   int left = end - start;
-  target_row(y, xt);
-  nk = ta - H;
+  target_row(y, xtile(xg));
+  nk = ta - 1;
   {
     int xi = nxs;
-    unsigned e = first();
+    unsigned e[2] = {first(nk), first(nk + 1)};
 #pragma unroll
     for (int s = 0; s < KS; ++s) load_step(s, xi, e);
   }
   while (left > 0) {
-    // piece: tiles [ta, tb) of row (y, xt), chunks [ta - H, tb + H)
+    // piece: tiles [ta, tb) of row (y, xt); pairs of chunks from ta - 1,
+    // the last one possibly reaching one chunk past tb
     const int tb = left < p.nct - ta ? ta + left : p.nct;
     left -= tb - ta;
+    const int xt = xtile(xg);
+    const bool drop = 4 * xg + wave >= p.nxt;
     const int x0 = 16 * xt;
     const float ms = a.mshift[y];
-    const int ke = tb + H;
-    int k = ta - H;
-    // the chunk after k: the next one of this piece, else the first one of
+    int k = ta - 1;   // first chunk of the pair in b
+    // the pair after k: the next one of this piece, else the first one of
     // the next row, else k again (a harmless reload)
     auto aim = [&]() XZM_INLINE {
-      if (k + 1 < ke) {
-        nk = k + 1;
+      if (k + 2 <= tb) {
+        nk = k + 2;
       } else if (left > 0) {
-        const bool wrap = xt + 1 == p.nxt;
-        target_row(wrap ? y + 1 : y, wrap ? 0 : xt + 1);
-        nk = -H;
+        const bool wrap = xg + 1 == p.nxg;
+        target_row(wrap ? y + 1 : y, xtile(wrap ? 0 : xg + 1));
+        nk = -1;
       } else {
         nk = k;
       }
     };
-    // chunks ta - H .. ta + H into slots 0 .. 2H
-    static_for<0, NW>([&](auto q) XZM_INLINE {
-      aim();
-      xfilter(q, ms);
-      ++k;
-    });
-    // each step: z stencil of the tile whose last chunk is the newest one,
-    // then the x stencil of the next chunk. Every step ends with the next
-    // chunk's loads, also on entry, so the waits for them count the same
-    // stores on every path.
+    // pair 0 (chunks ta - 1, ta) into slots 0, 1
+    aim();
+    xfilter(std::integral_constant<int, 0>{}, ms);
+    k += 2;
+    // pair n (chunks ta - 1 + 2n, ta + 2n) completes tiles ta + 2n - 2 and
+    // ta + 2n - 1: the first reads slots 2n - 2 .. 2n, the second 2n - 1 ..
+    // 2n + 1 (mod 4)
     bool done = false;
     while (!done) {
-      static_for<0, NW>([&](auto q) XZM_INLINE {
-        constexpr int S = (2 * H + decltype(q)::value) % NW;
+      static_for<0, 2>([&](auto q) XZM_INLINE {
+        constexpr int S = 2 * ((decltype(q)::value + 1) % 2);   // slots of this pair: S, S + 1
         if (done) return;
-        zfilter(std::integral_constant<int, S>{}, k - 1 - H, y, x0);
-        if (k == ke) {
-          done = true;
-          return;
-        }
         aim();
-        xfilter(std::integral_constant<int, (S + 1) % NW>{}, ms);
-        ++k;
+        xfilter(std::integral_constant<int, S>{}, ms);
+        const int t = k - 1;   // first tile this pair completes
+        k += 2;
+        zfilter(std::integral_constant<int, (S + 2) % NR>{}, t, y, x0, drop);
+        if (t + 1 < tb) zfilter(std::integral_constant<int, (S + 3) % NR>{}, t + 1, y, x0, drop);
+        if (t + 2 >= tb) done = true;
       });
     }
-    if (++xt == p.nxt) {
-      xt = 0;
+    if (++xg == p.nxg) {
+      xg = 0;
       ++y;
     }
     ta = 0;
@@ -282,10 +309,10 @@ __global__ void __launch_bounds__(kWaves * 64) __attribute__((amdgpu_waves_per_e
 
 using KernelFn = void (*)(XzArgs, XzmPlan);
 
-// instances for x stencil steps 5..12 (H = 1), with and without 16-byte stores
+// instances for x stencil steps 5..12, with and without 16-byte stores
 template <int KS, bool VEC>
 constexpr KernelFn kernel_of() {
-  return k_xzm<KS, 1, VEC>;
+  return k_xzm<KS, VEC>;
 }
 template <bool VEC>
 KernelFn pick(int ks) {
@@ -315,8 +342,9 @@ bool xzm_plan(int nx, int ny, int nz, int mx, int mz, XzmPlan *p) {
   p->h = 1;
   p->vec = (nz & 3) == 0;
   p->nxt = (nx + 15) / 16;
+  p->nxg = (p->nxt + kWaves - 1) / kWaves;
   p->nct = (nz + 15) / 16;
-  p->nrow = p->nxt * ny;
+  p->nrow = p->nxg * ny;
   int dev = 0, ncu = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -324,9 +352,9 @@ bool xzm_plan(int nx, int ny, int nz, int mx, int mz, XzmPlan *p) {
   const KernelFn fn = pick(p->ks, p->vec);
   if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWaves * 64, 0) != hipSuccess) return false;
   if (per_cu < 1 || ncu < 1) return false;
-  // every resident wave takes an equal share, at least two tiles each
+  // every resident block takes an equal share, at least two positions each
   const long tiles = (long)p->nrow * p->nct;
-  const long want = (tiles + 2 * kWaves - 1) / (2 * kWaves);
+  const long want = (tiles + 1) / 2;
   const long cap = (long)per_cu * ncu;
   p->nblk = (int)(want < cap ? want : cap);
   return true;
