@@ -174,6 +174,37 @@ def test_sgs_stress_matches_oracle(E, label, base, over, seed, route, xz):
         assert np.all(np.abs(st[q] - ref[q]) <= rms * (1 + 1e-9) + 1e-14), q
 
 
+# Wide stencils (x/z half-widths above 16, beyond the matrix-core x/z
+# kernel's window): the vector-unit x/z pass.
+# Boxes shrunk with the grid so that the widths keep their size in grid
+# steps: sigma/dx = 2.31 as at 192 x 129 x 192 (half-widths 20, z window of
+# five chunks), and 6.2 as at 1024 x 385 x 768 (half-widths 37, seven chunks).
+WIDE_CASES = [
+    # label, base, overrides, seed, tail
+    ("h2", "dns192", dict(nx=40, nz=48, ny=33, lx=4 * math.pi * 40 / 192, lz=2 * math.pi * 48 / 192), 5, 0.0),
+    ("h3", "dns192", dict(nx=40, nz=64, ny=17, lx=40 * 0.151 / 6.2, lz=64 * 0.0756 / 6.2), 6, 1e-8),
+    ("ragged_x", "dns192", dict(nx=27, nz=36, ny=21, lx=4 * math.pi * 27 / 192, lz=2 * math.pi * 36 / 192), 7,
+     0.0),
+]
+
+
+@pytest.mark.parametrize("label,base,over,seed,tail", WIDE_CASES)
+def test_sgs_wide_stencils(E, label, base, over, seed, tail):
+    cfg = synth.config(base, **over)
+    y, u, ub, tau, st, f = _sgs_case(E, cfg, seed, tail)
+    assert f.layout.xz_waves == 0 and min(f.layout.mx, f.layout.mz) > 16, (label, f.layout.mx, f.layout.mz)
+    ops = R.Operators.from_config(cfg, tail_tol=tail)
+    rub, rtau = R.sgs_stress(u.astype(np.float64), ops)
+    tol = fp32_tolerances(u, ops, y)
+    for k in range(3):
+        assert _rel(ub[k], rub[k], y) < 1e-5, ("ubar", k)
+    for k in range(6):
+        err = _rel(tau[k], rtau[k], y)
+        print(label, f"m=({f.layout.mx},{f.layout.mz})", "tau", R.PAIRS[k], f"{err:.2e} (tol {tol[k]:.1e})",
+              flush=True)
+        assert err < tol[k], ("tau", k, err)
+
+
 def test_sgs_dns192_full_size(E):
     """The 192 x 129 x 192 channel at its own widths, FP32 path, seeds 0-1,
     with the full kernel and with the 1e-8 tail cut the benchmark uses (both
