@@ -101,6 +101,9 @@ typedef struct {
   int32_t xz_waves;            /* waves of the matrix-core stress x/z pass;
                                   0 when this grid uses the vector-unit
                                   x/z pass instead                            */
+  int32_t xz_wide;             /* 1 when that pass is the wide-stencil kernel
+                                  (three of the nine fields per wave: x or z
+                                  half-width above 16)                        */
 } eles_state_layout;
 
 /* Human-readable name of a status code. Never NULL. */
@@ -124,8 +127,9 @@ int32_t filter_set_ygemm(eles_filter f, int32_t ygemm);
 
 /* Choose how later sgs_stress calls evaluate the periodic x and z parts of
  * the filter (Sec. 2.1, eq. (2)) on the nine fields: 1 = on the matrix cores
- * (the default wherever that kernel covers the grid: x and z stencil
- * half-widths up to 16, nx >= 4), 0 = on the vector units. Both give the
+ * (the default wherever those kernels cover the grid: nx >= 4 and either x
+ * and z stencil half-widths up to 16, or half-widths up to 44 in x and 48
+ * in z with nz % 4 == 0), 0 = on the vector units. Both give the
  * same result up to FP32 rounding order. Errors: EINVAL (null handle, value
  * other than 0 or 1), ENOTSUP (1 asked for a grid the matrix-core kernel
  * does not cover; the setting is left unchanged). */

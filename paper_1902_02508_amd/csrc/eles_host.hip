@@ -411,6 +411,7 @@ int32_t filter_setup(const eles_filter_desc *desc, void *state, size_t state_byt
   L.y_blocks = f->ys_ok ? f->ys.nblk : 0;
   f->xzm_ok = eles::xzm_plan(desc->nx, desc->ny, desc->nz, p.mx, p.mz, &f->xzm);
   L.xz_waves = f->xzm_ok ? f->xzm.nblk * eles::kXzmWaves : 0;
+  L.xz_wide = f->xzm_ok && f->xzm.wide ? 1 : 0;
   *out = f;
   return ELES_OK;
 }

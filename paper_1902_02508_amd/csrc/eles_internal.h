@@ -68,11 +68,13 @@ int xz_tile_z(int nz, int mz);
 // the waves of a block take the group's neighbouring 16-row x tiles.
 constexpr int kXzmWaves = 4;   // waves per block of the matrix-core x/z pass
 struct XzmPlan {
+  int wide;   // 0: k_xzm (nine fields a wave); 1: k_xzw (three fields a wave)
   int ks;     // x stencil steps of four input rows (covers 16 + 2 mx rows)
   int h;      // z chunks on each side of a tile (covers mz)
   int vec;    // nz % 4 == 0: 16-byte stores
   int nxt;    // 16-row x tiles
-  int nxg;    // groups of kXzmWaves x tiles (one per wave of a block)
+  int nxg;    // k_xzm: groups of kXzmWaves x tiles (one per wave of a block);
+              // k_xzw: block rows of kXzmWaves (x tile, field group) items
   int nct;    // 16-column z tiles
   int nrow;   // rows: ny * nxg
   int nblk;   // blocks of kXzmWaves waves
@@ -81,6 +83,14 @@ struct XzmPlan {
 // k_xz then runs instead).
 bool xzm_plan(int nx, int ny, int nz, int mx, int mz, XzmPlan *p);
 hipError_t launch_xzm(const XzArgs &a, const XzmPlan &p, hipStream_t s);
+
+// Wide stencils (k_xzw.hip): x half-width up to 44, z up to 48, nz % 4 == 0.
+// Each wave carries one group of three of the nine fields for one 16-row x
+// tile; a block's four waves take four consecutive (x tile, group) items.
+constexpr int kXzwMaxSteps = 26;   // x stencil steps of four rows
+constexpr int kXzwMaxHalo = 3;     // z chunks on each side of a tile
+bool xzw_plan(int nx, int ny, int nz, int mx, int mz, XzmPlan *p);
+hipError_t launch_xzw(const XzArgs &a, const XzmPlan &p, hipStream_t s);
 
 // y pass, k_y.hip.
 struct YArgs {

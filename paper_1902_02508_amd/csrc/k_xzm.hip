@@ -334,7 +334,9 @@ KernelFn pick(int ks, bool vec) { return vec ? pick<true>(ks) : pick<false>(ks);
 
 bool xzm_plan(int nx, int ny, int nz, int mx, int mz, XzmPlan *p) {
   const int ks = (16 + 2 * mx + 3) / 4;
-  if (mz > 16 || ks > 12 || nx < 4) return false;
+  if (mz > 16 || ks > 12) return xzw_plan(nx, ny, nz, mx, mz, p);
+  if (nx < 4) return false;
+  p->wide = 0;
   if ((long)nx * ny * nz >= (1L << 29)) return false;   // byte offsets below 2^31
   // byte offsets of sixteen output x rows below 2^31 (buffer stores)
   if (16L * ny * 9 * nz * 4 >= (1L << 31)) return false;
@@ -361,6 +363,7 @@ bool xzm_plan(int nx, int ny, int nz, int mx, int mz, XzmPlan *p) {
 }
 
 hipError_t launch_xzm(const XzArgs &a, const XzmPlan &p, hipStream_t s) {
+  if (p.wide) return launch_xzw(a, p, s);
   const KernelFn fn = pick(p.ks, p.vec);
   if (!fn) return hipErrorInvalidValue;
   fn<<<(unsigned)p.nblk, kWaves * 64, 0, s>>>(a, p);

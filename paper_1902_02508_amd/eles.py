@@ -42,7 +42,7 @@ class StateLayout(ctypes.Structure):
         ("off_y64", ctypes.c_size_t), ("off_shift", ctypes.c_size_t),
         ("state_bytes", ctypes.c_size_t),
         ("y_groups", ctypes.c_int32), ("y_blocks", ctypes.c_int32),
-        ("xz_waves", ctypes.c_int32),
+        ("xz_waves", ctypes.c_int32), ("xz_wide", ctypes.c_int32),
     ]
 
 

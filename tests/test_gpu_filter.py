@@ -174,8 +174,9 @@ def test_sgs_stress_matches_oracle(E, label, base, over, seed, route, xz):
         assert np.all(np.abs(st[q] - ref[q]) <= rms * (1 + 1e-9) + 1e-14), q
 
 
-# Wide stencils (x/z half-widths above 16, beyond the matrix-core x/z
-# kernel's window): the vector-unit x/z pass.
+# Wide stencils (x/z half-widths above 16): the matrix-core wide kernel
+# (three of the nine fields per wave, z windows of up to seven 16-column
+# chunks) and the vector-unit x/z pass.
 # Boxes shrunk with the grid so that the widths keep their size in grid
 # steps: sigma/dx = 2.31 as at 192 x 129 x 192 (half-widths 20, z window of
 # five chunks), and 6.2 as at 1024 x 385 x 768 (half-widths 37, seven chunks).
@@ -189,10 +190,12 @@ WIDE_CASES = [
 
 
 @pytest.mark.parametrize("label,base,over,seed,tail", WIDE_CASES)
-def test_sgs_wide_stencils(E, label, base, over, seed, tail):
+@pytest.mark.parametrize("xz", ["matrix", "vector"])
+def test_sgs_wide_stencils(E, label, base, over, seed, tail, xz):
     cfg = synth.config(base, **over)
-    y, u, ub, tau, st, f = _sgs_case(E, cfg, seed, tail)
-    assert f.layout.xz_waves == 0 and min(f.layout.mx, f.layout.mz) > 16, (label, f.layout.mx, f.layout.mz)
+    y, u, ub, tau, st, f = _sgs_case(E, cfg, seed, tail, xz=xz)
+    assert min(f.layout.mx, f.layout.mz) > 16, (label, f.layout.mx, f.layout.mz)
+    assert f.layout.xz_waves > 0 and f.layout.xz_wide == 1, label
     ops = R.Operators.from_config(cfg, tail_tol=tail)
     rub, rtau = R.sgs_stress(u.astype(np.float64), ops)
     tol = fp32_tolerances(u, ops, y)
