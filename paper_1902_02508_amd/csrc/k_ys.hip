@@ -50,13 +50,19 @@ namespace eles {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+// word 3 of a raw buffer descriptor on gfx9-family parts (32-bit data
+// format, no swizzle)
+constexpr int kBufWord3 = 0x00020000;
 
 constexpr int RS = kYsRow;
 constexpr int kSlots = 36;        // float4 slots per staged row: 9 fields x 4
 constexpr int kIo = 256;          // I/O threads (waves 4..7)
 constexpr int kBlock = 512;
 constexpr int kMaxT = 3;          // tiles per group
-constexpr int kKR = 10;           // staged float4 slots per I/O thread held in registers
+// staged float4 slots per I/O thread held in registers (KR, a template
+// parameter): the smallest instantiated count that covers the widest group,
+// so the commit normally needs no load of its own
+constexpr int kKRs[] = {10, 14, 18};
 static_assert(16 * kMaxT * 4 <= kIo, "one epilogue slot per I/O thread");
 static_assert(kMaxT <= kYsMaxTiles, "tile bound");
 
@@ -98,13 +104,18 @@ __device__ inline f4 load_slot(const YArgs &a, Pencil m, int kb, int nrow, int q
   const int f = rem >> 2, zl = 4 * (rem & 3);
   const int z0 = m.strip * kYTileN;
   const bool rok = kb + row < a.ny;
+  if (VEC) {
+    // through a buffer descriptor of the pencil's x slab: 32-bit offsets,
+    // and rows past ny or columns past nz read as zeros (offset outside)
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(a.in + (size_t)m.x * a.in_xs), 0, (int)(a.in_xs * 4), kBufWord3);
+    const bool ok = qok && rok && z0 + zl < a.nz;
+    const unsigned off = ok ? (unsigned)(((kb + row) * a.in_ks + f * a.in_fs + z0 + zl) * 4) : 0x80000000u;
+    *zero = false;
+    return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+  }
   const float *p = a.in + (size_t)m.x * a.in_xs + (size_t)(kb + (rok ? row : 0)) * a.in_ks +
                    (size_t)f * a.in_fs + z0;
-  if (VEC) {
-    const bool ok = rok && z0 + zl < a.nz;
-    *zero = !ok;
-    return *reinterpret_cast<const f4 *>(p + (ok ? zl : 0));
-  }
   // ragged z: four scalar loads, columns past nz zeroed here (rare shape)
   f4 v;
 #pragma unroll
@@ -122,11 +133,11 @@ __device__ inline void store_slot(float *sx, int q, const f4 &v) {
   *reinterpret_cast<f4 *>(sx + row * RS + (rem >> 2) * 16 + 4 * (rem & 3)) = v;
 }
 
-template <bool VEC>
-__device__ inline unsigned prefetch(const YArgs &a, Pencil m, int kb, int nrow, int io, f4 (&r)[kKR]) {
+template <bool VEC, int KR>
+__device__ inline unsigned prefetch(const YArgs &a, Pencil m, int kb, int nrow, int io, f4 (&r)[KR]) {
   unsigned zmask = 0;
 #pragma unroll
-  for (int u = 0; u < kKR; ++u) {
+  for (int u = 0; u < KR; ++u) {
     bool z;
     r[u] = load_slot<VEC>(a, m, kb, nrow, u * kIo + io, &z);
     zmask |= (unsigned)z << u;
@@ -135,27 +146,27 @@ __device__ inline unsigned prefetch(const YArgs &a, Pencil m, int kb, int nrow, 
 }
 
 // Registers to LDS, then any slots past the register window straight from HBM.
-template <bool VEC>
-__device__ inline void commit(const YArgs &a, Pencil m, int kb, int nrow, int io, const f4 (&r)[kKR],
+template <bool VEC, int KR>
+__device__ inline void commit(const YArgs &a, Pencil m, int kb, int nrow, int io, const f4 (&r)[KR],
                               unsigned zmask, float *sx) {
   const int nq = nrow * kSlots;
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int u = 0; u < kKR; ++u) {
+  for (int u = 0; u < KR; ++u) {
     const int q = u * kIo + io;
     if (q < nq) store_slot(sx, q, (zmask >> u) & 1u ? zero : r[u]);
   }
-  for (int base = kKR * kIo; base < nq; base += kKR * kIo) {
-    f4 v[kKR];
+  for (int base = KR * kIo; base < nq; base += KR * kIo) {
+    f4 v[KR];
     unsigned zm = 0;
 #pragma unroll
-    for (int u = 0; u < kKR; ++u) {
+    for (int u = 0; u < KR; ++u) {
       bool z;
       v[u] = load_slot<VEC>(a, m, kb, nrow, base + u * kIo + io, &z);
       zm |= (unsigned)z << u;
     }
 #pragma unroll
-    for (int u = 0; u < kKR; ++u) {
+    for (int u = 0; u < KR; ++u) {
       const int q = base + u * kIo + io;
       if (q < nq) store_slot(sx, q, (zm >> u) & 1u ? zero : v[u]);
     }
@@ -165,7 +176,7 @@ __device__ inline void commit(const YArgs &a, Pencil m, int kb, int nrow, int io
 // LDS layout of a block: operator tiles [4 ops][group chunks][64 lanes][4],
 // staged rows X [lds_rows][RS], products Y [16 kMaxT][RS], then M and S of
 // the group's rows [2][16 kMaxT].
-template <bool VEC>
+template <bool VEC, int KR>
 __global__ void __launch_bounds__(kBlock, 1) k_ys(YArgs a, YsPlan pl) {
   extern __shared__ float lds[];
   const int tid = threadIdx.x;
@@ -385,10 +396,10 @@ __global__ void __launch_bounds__(kBlock, 1) k_ys(YArgs a, YsPlan pl) {
   };
 
   Pencil cur{p / a.n16, p % a.n16};
-  f4 rv[kKR];
-  unsigned zm = prefetch<VEC>(a, cur, kb, nrow, io, rv);
+  f4 rv[KR];
+  unsigned zm = prefetch<VEC, KR>(a, cur, kb, nrow, io, rv);
   __syncthreads();   // operator tiles and profiles are in LDS
-  commit<VEC>(a, cur, kb, nrow, io, rv, zm, sx);
+  commit<VEC, KR>(a, cur, kb, nrow, io, rv, zm, sx);
   __syncthreads();
   bool have_prev = false;
   Pencil prev = cur;
@@ -399,11 +410,11 @@ __global__ void __launch_bounds__(kBlock, 1) k_ys(YArgs a, YsPlan pl) {
     // ---- phase 1: next rows in flight, epilogue of the previous pencil
     // (unconditional: the last pencil re-reads itself, which keeps the
     // compiler's count of outstanding memory operations exact)
-    zm = prefetch<VEC>(a, nxt, kb, nrow, io, rv);
+    zm = prefetch<VEC, KR>(a, nxt, kb, nrow, io, rv);
     if (have_prev) epilogue(prev);
     __syncthreads();
     // ---- phase 2: next rows to X
-    if (more) commit<VEC>(a, nxt, kb, nrow, io, rv, zm, sx);
+    if (more) commit<VEC, KR>(a, nxt, kb, nrow, io, rv, zm, sx);
     __syncthreads();
     prev = cur;
     have_prev = true;
@@ -419,8 +430,32 @@ __global__ void __launch_bounds__(kBlock, 1) k_ys(YArgs a, YsPlan pl) {
 }
 
 template <bool VEC>
-const void *ys_fn() {
-  return (const void *)k_ys<VEC>;
+const void *ys_fn(int kr) {
+  if (!VEC) return (const void *)k_ys<false, 10>;
+  switch (kr) {
+    case 10: return (const void *)k_ys<true, 10>;
+    case 14: return (const void *)k_ys<true, 14>;
+    default: return (const void *)k_ys<true, 18>;
+  }
+}
+
+// register window of the plan: the smallest instantiated KR with
+// KR * kIo >= the widest group's staged slots (else the largest; the commit
+// then loads the remainder itself)
+int ys_kr(const YsPlan &p) {
+  int slots = 0;
+  for (int g = 0; g < p.ngroup; ++g) slots = max(slots, p.nrow[g] * kSlots);
+  for (int kr : kKRs)
+    if (kr * kIo >= slots) return kr;
+  return kKRs[2];
+}
+
+// ragged nz (scalar loads, rare shapes) keeps the smallest window
+int ys_kr(const YsPlan &p, int nz) { return nz % 4 == 0 ? ys_kr(p) : kKRs[0]; }
+
+const void *ys_pick(const YsPlan &p, int nz) {
+  const int kr = ys_kr(p, nz);
+  return (nz % 4) == 0 ? ys_fn<true>(kr) : ys_fn<false>(kr);
 }
 
 }  // namespace
@@ -434,7 +469,7 @@ size_t ys_lds_bytes(const YsPlan &p) {
 
 int ys_grid(const YsPlan &p, int nz, int npencils) {
   const size_t lds = ys_lds_bytes(p);
-  const void *fn = (nz % 4) == 0 ? ys_fn<true>() : ys_fn<false>();
+  const void *fn = ys_pick(p, nz);
   if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   int per = 0, dev = 0, ncu = 0;
@@ -450,10 +485,16 @@ int ys_grid(const YsPlan &p, int nz, int npencils) {
 hipError_t launch_ys(const YArgs &a, const YsPlan &p, hipStream_t s) {
   const size_t lds = ys_lds_bytes(p);
   if (p.nblk < p.ngroup || p.nblk % p.ngroup) return hipErrorInvalidValue;
-  if (a.nz % 4 == 0)
-    k_ys<true><<<(unsigned)p.nblk, kBlock, lds, s>>>(a, p);
-  else
-    k_ys<false><<<(unsigned)p.nblk, kBlock, lds, s>>>(a, p);
+  const int kr = ys_kr(p, a.nz);
+  if (a.nz % 4 == 0) {
+    switch (kr) {
+      case 10: k_ys<true, 10><<<(unsigned)p.nblk, kBlock, lds, s>>>(a, p); break;
+      case 14: k_ys<true, 14><<<(unsigned)p.nblk, kBlock, lds, s>>>(a, p); break;
+      default: k_ys<true, 18><<<(unsigned)p.nblk, kBlock, lds, s>>>(a, p); break;
+    }
+  } else {
+    k_ys<false, 10><<<(unsigned)p.nblk, kBlock, lds, s>>>(a, p);
+  }
   return hipGetLastError();
 }
 
