@@ -179,6 +179,64 @@ int32_t filter_profile_end(eles_filter f, double *ms /* [ELES_NPASS] */,
 void filter_destroy(eles_filter f);
 
 /* ======================================================================
+ * The paper's own filter: Germano's differential filter (Sec. 3,
+ * eq. (12)), the kernel exp(-|r|/a) / (4 pi a^2 |r|) of parameter a. It is
+ * the free-space Green's function of (1 - a^2 lap), so the filtered field
+ * solves (1 - a^2 lap) ubar = u. Discretisation (the paper states none):
+ * spectral second derivatives in the periodic x and z directions (symbol
+ * -k^2 on the grid wavenumbers), and in y the three-point second
+ * difference on the non-uniform nodes of the flow reflected across each
+ * wall as in eq. (7): an even field takes the mirrored value at the mirror
+ * node, an odd field is zero at the wall nodes (eqs. (8), (11)). Layouts,
+ * ownership, streams and errors as for the Gaussian filter above.
+ * ====================================================================== */
+typedef struct {
+  int32_t nx, ny, nz;     /* nx, nz >= 2; ny >= 4                               */
+  double lx, lz;          /* periodic lengths, > 0                              */
+  const double *y;        /* host, ny values, strictly increasing,
+                             y[0] = -1 and y[ny-1] = +1 exactly (the walls)     */
+  double a;               /* filter parameter, > 0 (the paper: 0.1)            */
+} eles_dfilter_desc;
+
+typedef struct eles_dfilter_s *eles_dfilter;
+
+/* Device bytes of the state of this descriptor; 0 if it is invalid. */
+size_t dfilter_state_bytes(const eles_dfilter_desc *desc);
+
+/* Build the operators on the device in FP64 (rounded to FP32 where the
+ * kernels read them): the real Fourier transforms of x and z, and the
+ * factors of the wall-normal tridiagonal system of every wavenumber pair
+ * and parity. Waits for the stream. Errors: EINVAL, ENOSPACE, ENOTSUP
+ * (grid too large for 32-bit offsets), EHIP. */
+int32_t dfilter_setup(const eles_dfilter_desc *desc, void *state, size_t state_bytes, hipStream_t stream,
+                      eles_dfilter *out);
+
+/* Workspace bytes of dfilter_fields with nfields fields, and of
+ * dfilter_sgs_stress. */
+size_t dfilter_workspace_bytes(eles_dfilter f, int32_t nfields);
+size_t dfilter_sgs_workspace_bytes(eles_dfilter f);
+
+/* out[k] = F^(s_k)(in[k]), the differential filter of a field of parity
+ * s_k = parity[k] in {+1, -1} (host array). in, out: device
+ * [nfields][nx][ny][nz], not overlapping; 1 <= nfields <= 32. An odd
+ * field's input values on the wall planes are not read into the solve and
+ * its output there is exactly 0. Errors: EINVAL (also a parity other than
+ * +-1), ENOSPACE, EHIP. */
+int32_t dfilter_fields(eles_dfilter f, const float *in, int32_t nfields, const int8_t *parity, float *out,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Filtered velocity and exact subgrid stress with the differential filter
+ * (Sec. 2.1, four steps); arguments as for sgs_stress. u1 is shifted by
+ * its plane-mean profile m(y) before the products are formed; the terms
+ * the shift leaves (F(m u_j) - F(m) F(u_j), F(m^2) - F(m)^2) are filtered
+ * with the rest, so the result is the exact stress of the unshifted
+ * field. Errors: EINVAL, ENOSPACE, EHIP. */
+int32_t dfilter_sgs_stress(eles_dfilter f, const float *u, float *ubar, float *tau, double *stats, void *ws,
+                           size_t ws_bytes, hipStream_t stream);
+
+void dfilter_destroy(eles_dfilter f);
+
+/* ======================================================================
  * Learned closure of the exact stress.
  *
  * The paper proposes using the exact stress computed from DNS data to

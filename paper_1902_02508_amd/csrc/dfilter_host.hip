@@ -1,0 +1,191 @@
+// Host side of the differential-filter part of the C ABI (include/eles.h):
+// descriptor validation, layout of the caller-owned state and workspace,
+// and the launch sequence of each call. Every step of the filter runs in
+// the kernels of k_dfilt.hip.
+#include "eles.h"
+#include "eles_internal.h"
+
+#include <cmath>
+#include <new>
+#include <vector>
+
+struct eles_dfilter_s {
+  eles_dfilter_desc d;
+  std::vector<double> y;
+  eles::DView v;
+  size_t npts;
+};
+
+namespace {
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+  const char *pa = (const char *)a, *pb = (const char *)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+enum { D_Y, D_D64, D_S64, D_TX, D_ITX, D_TZ, D_ITZ, D_LO, D_CP, D_INV, D_PROF, D_END };
+
+struct DPlan {
+  int qpx, kpx, qpz, kpz, hx, hz;
+  size_t off[D_END];
+  size_t bytes;
+};
+
+int32_t plan_d(const eles_dfilter_desc *d, DPlan *p) {
+  if (!d || !d->y) return ELES_EINVAL;
+  if (d->nx < 2 || d->nz < 2 || d->ny < 4 || d->ny > 8192) return ELES_EINVAL;
+  if (!(std::isfinite(d->lx) && d->lx > 0) || !(std::isfinite(d->lz) && d->lz > 0)) return ELES_EINVAL;
+  if (!(std::isfinite(d->a) && d->a > 0)) return ELES_EINVAL;
+  const double *y = d->y;
+  if (y[0] != -1.0 || y[d->ny - 1] != 1.0) return ELES_EINVAL;
+  for (int j = 0; j < d->ny; ++j)
+    if (!std::isfinite(y[j]) || (j > 0 && !(y[j] > y[j - 1]))) return ELES_EINVAL;
+  // the kernels count grid points, columns and rows in 32-bit integers
+  if ((double)d->nx * d->ny * d->nz > 2147483647.0) return ELES_ENOTSUP;
+  p->qpx = (d->nx + 15) / 16 * 16;
+  p->kpx = (d->nx + 3) / 4 * 4;
+  p->qpz = (d->nz + 15) / 16 * 16;
+  p->kpz = (d->nz + 3) / 4 * 4;
+  p->hx = d->nx / 2;
+  p->hz = d->nz / 2;
+  const size_t ny = d->ny;
+  const size_t nfac = 2 * (size_t)(p->hx + 1) * (p->hz + 1) * ny;
+  const size_t sz[D_END] = {ny * 8,
+                            6 * ny * 8,
+                            3 * ny * 8,
+                            (size_t)p->qpx * p->kpx * 4,
+                            (size_t)p->qpx * p->kpx * 4,
+                            (size_t)p->qpz * p->kpz * 4,
+                            (size_t)p->qpz * p->kpz * 4,
+                            2 * ny * 4,
+                            nfac * 4,
+                            nfac * 4,
+                            3 * ny * 4};
+  size_t o = 0;
+  for (int k = 0; k < D_END; ++k) {
+    p->off[k] = o;
+    o += up256(sz[k]);
+  }
+  p->bytes = o;
+  return ELES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dfilter_state_bytes(const eles_dfilter_desc *desc) {
+  DPlan p;
+  return plan_d(desc, &p) == ELES_OK ? p.bytes : 0;
+}
+
+int32_t dfilter_setup(const eles_dfilter_desc *desc, void *state, size_t state_bytes, hipStream_t stream,
+                      eles_dfilter *out) {
+  if (!out) return ELES_EINVAL;
+  DPlan p;
+  const int32_t st = plan_d(desc, &p);
+  if (st != ELES_OK) return st;
+  if (!state || !aligned16(state)) return ELES_EINVAL;
+  if (state_bytes < p.bytes) return ELES_ENOSPACE;
+  eles_dfilter_s *f = new (std::nothrow) eles_dfilter_s;
+  if (!f) return ELES_EINVAL;
+  f->d = *desc;
+  f->y.assign(desc->y, desc->y + desc->ny);
+  f->d.y = f->y.data();
+  f->npts = (size_t)desc->nx * desc->ny * desc->nz;
+  char *s = (char *)state;
+  eles::DView &v = f->v;
+  v.nx = desc->nx;
+  v.ny = desc->ny;
+  v.nz = desc->nz;
+  v.hx = p.hx;
+  v.hz = p.hz;
+  v.qpx = p.qpx;
+  v.kpx = p.kpx;
+  v.qpz = p.qpz;
+  v.kpz = p.kpz;
+  v.lx = desc->lx;
+  v.lz = desc->lz;
+  v.a = desc->a;
+  v.y64 = (double *)(s + p.off[D_Y]);
+  v.d64 = (double *)(s + p.off[D_D64]);
+  v.scratch64 = (double *)(s + p.off[D_S64]);
+  v.tx = (float *)(s + p.off[D_TX]);
+  v.itx = (float *)(s + p.off[D_ITX]);
+  v.tz = (float *)(s + p.off[D_TZ]);
+  v.itz = (float *)(s + p.off[D_ITZ]);
+  v.lo32 = (float *)(s + p.off[D_LO]);
+  v.cp = (float *)(s + p.off[D_CP]);
+  v.inv = (float *)(s + p.off[D_INV]);
+  v.prof = (float *)(s + p.off[D_PROF]);
+  if (hipMemcpyAsync(v.y64, f->y.data(), f->y.size() * sizeof(double), hipMemcpyHostToDevice, stream) !=
+          hipSuccess ||
+      eles::launch_dsetup(v, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
+    delete f;
+    return ELES_EHIP;
+  }
+  *out = f;
+  return ELES_OK;
+}
+
+size_t dfilter_workspace_bytes(eles_dfilter f, int32_t nfields) {
+  if (!f || nfields < 1 || nfields > 32) return 0;
+  return 2 * up256((size_t)nfields * f->npts * sizeof(float));
+}
+
+size_t dfilter_sgs_workspace_bytes(eles_dfilter f) {
+  if (!f) return 0;
+  return 2 * up256((size_t)eles::kDFields * f->npts * sizeof(float)) +
+         up256((size_t)eles::plane_mean_parts(6, f->d.ny) * sizeof(double));
+}
+
+int32_t dfilter_fields(eles_dfilter f, const float *in, int32_t nfields, const int8_t *parity, float *out,
+                       void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!f || !in || !out || !parity || !ws || nfields < 1 || nfields > 32) return ELES_EINVAL;
+  if (!aligned16(in) || !aligned16(out) || !aligned16(ws)) return ELES_EINVAL;
+  unsigned pmask = 0;
+  for (int k = 0; k < nfields; ++k) {
+    if (parity[k] != 1 && parity[k] != -1) return ELES_EINVAL;
+    if (parity[k] < 0) pmask |= 1u << k;
+  }
+  const size_t bytes = (size_t)nfields * f->npts * sizeof(float);
+  if (overlap(in, bytes, out, bytes)) return ELES_EINVAL;
+  if (ws_bytes < dfilter_workspace_bytes(f, nfields)) return ELES_ENOSPACE;
+  if (overlap(ws, ws_bytes, in, bytes) || overlap(ws, ws_bytes, out, bytes)) return ELES_EINVAL;
+  float *w0 = (float *)ws;
+  float *w1 = (float *)((char *)ws + up256(bytes));
+  return eles::launch_dfilter(f->v, in, nfields, pmask, w0, w1, out, stream) == hipSuccess ? ELES_OK : ELES_EHIP;
+}
+
+int32_t dfilter_sgs_stress(eles_dfilter f, const float *u, float *ubar, float *tau, double *stats, void *ws,
+                           size_t ws_bytes, hipStream_t stream) {
+  if (!f || !u || !ubar || !tau || !ws) return ELES_EINVAL;
+  if (!aligned16(u) || !aligned16(ubar) || !aligned16(tau) || !aligned16(ws)) return ELES_EINVAL;
+  if (stats && ((uintptr_t)stats & 7u)) return ELES_EINVAL;
+  const size_t n = f->npts;
+  if (overlap(u, 3 * n * 4, ubar, 3 * n * 4) || overlap(u, 3 * n * 4, tau, 6 * n * 4) ||
+      overlap(ubar, 3 * n * 4, tau, 6 * n * 4))
+    return ELES_EINVAL;
+  if (ws_bytes < dfilter_sgs_workspace_bytes(f)) return ELES_ENOSPACE;
+  if (overlap(ws, ws_bytes, u, 3 * n * 4) || overlap(ws, ws_bytes, ubar, 3 * n * 4) ||
+      overlap(ws, ws_bytes, tau, 6 * n * 4))
+    return ELES_EINVAL;
+  const size_t fb = up256((size_t)eles::kDFields * n * sizeof(float));
+  float *w0 = (float *)ws;
+  float *w1 = (float *)((char *)ws + fb);
+  double *part = (double *)((char *)ws + 2 * fb);
+  if (eles::launch_dsgs(f->v, u, w0, w1, ubar, tau, stream) != hipSuccess) return ELES_EHIP;
+  if (stats) {
+    const int nx = f->d.nx, ny = f->d.ny, nz = f->d.nz;
+    if (eles::launch_plane_mean(ubar, 3, nx, ny, nz, part, stats, stream) != hipSuccess ||
+        eles::launch_plane_mean(tau, 6, nx, ny, nz, part, stats + 3 * ny, stream) != hipSuccess)
+      return ELES_EHIP;
+  }
+  return ELES_OK;
+}
+
+void dfilter_destroy(eles_dfilter f) { delete f; }
+
+}  // extern "C"

@@ -204,4 +204,26 @@ hipError_t launch_plane_mean(const float *f, int nq, int nx, int ny, int nz, dou
 hipError_t launch_train_step(const ClosureView &c, const TrainData &d, const TrainWs &w, uint64_t seed, long step,
                              int batch, AdamArgs adam, hipStream_t s);
 
+// Differential filter (k_dfilt.hip): real Fourier transforms along x and z
+// on the matrix cores, tridiagonal solves in y.
+constexpr int kDFields = 12;   // fields filtered for the stress
+struct DView {
+  int nx, ny, nz;
+  int hx, hz;                   // nx / 2, nz / 2: wavenumber indices 0 .. h
+  int qpx, kpx, qpz, kpz;       // transform matrices [qp][kp]: rows padded to 16, columns to 4
+  double lx, lz, a;
+  double *y64;                  // [ny]
+  double *d64;                  // [even, odd][sub, main, super][ny] second difference
+  double *scratch64;            // [3][ny]
+  float *tx, *itx, *tz, *itz;   // forward and inverse transforms
+  float *lo32;                  // [2][ny] system sub-diagonal -a^2 sub
+  float *cp, *inv;              // [2][hx + 1][hz + 1][ny] elimination factors
+  float *prof;                  // [3][ny] m, M = F(m), F(m^2) - M^2
+};
+hipError_t launch_dsetup(const DView &v, hipStream_t s);
+hipError_t launch_dfilter(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1, float *out,
+                          hipStream_t s);
+hipError_t launch_dsgs(const DView &v, const float *u, float *w0, float *w1, float *ubar, float *tau,
+                       hipStream_t s);
+
 }  // namespace eles

@@ -33,6 +33,15 @@ class FilterDesc(ctypes.Structure):
     ]
 
 
+class DFilterDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("lx", ctypes.c_double), ("lz", ctypes.c_double),
+        ("y", ctypes.POINTER(ctypes.c_double)),
+        ("a", ctypes.c_double),
+    ]
+
+
 class StateLayout(ctypes.Structure):
     _fields_ = [
         ("mx", ctypes.c_int32), ("mz", ctypes.c_int32),
@@ -67,6 +76,13 @@ _SIG = {
     "filter_profile_begin": (_I, [_P, _I]),
     "filter_profile_end": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)]),
     "filter_destroy": (None, [_P]),
+    "dfilter_state_bytes": (_S, [ctypes.POINTER(DFilterDesc)]),
+    "dfilter_setup": (_I, [ctypes.POINTER(DFilterDesc), _P, _S, _P, ctypes.POINTER(_P)]),
+    "dfilter_workspace_bytes": (_S, [_P, _I]),
+    "dfilter_sgs_workspace_bytes": (_S, [_P]),
+    "dfilter_fields": (_I, [_P, _P, _I, _P, _P, _P, _S, _P]),
+    "dfilter_sgs_stress": (_I, [_P, _P, _P, _P, _P, _P, _S, _P]),
+    "dfilter_destroy": (None, [_P]),
     "closure_state_bytes": (_S, []),
     "closure_create": (_I, [_P, _S, _P, _P, _P, ctypes.POINTER(_P)]),
     "closure_step": (ctypes.c_int64, [_P]),
@@ -466,3 +482,115 @@ def sample_indices(seed: int, step: int, batch: int, count: int, device="cuda") 
     out = torch.empty(batch, dtype=torch.int64, device=device)
     closure_sample_indices(seed, step, batch, count, _ptr(out), _stream())
     return out
+
+
+# ---- the paper's differential filter -------------------------------------
+
+def dfilter_state_bytes(desc: DFilterDesc) -> int:
+    return lib.dfilter_state_bytes(ctypes.byref(desc))
+
+
+def dfilter_setup(desc, state_ptr, state_bytes, stream) -> _P:
+    h = _P()
+    _check(lib.dfilter_setup(ctypes.byref(desc), state_ptr, state_bytes, stream, ctypes.byref(h)), "dfilter_setup")
+    return h
+
+
+def dfilter_workspace_bytes(h, nfields: int) -> int:
+    return lib.dfilter_workspace_bytes(h, nfields)
+
+
+def dfilter_sgs_workspace_bytes(h) -> int:
+    return lib.dfilter_sgs_workspace_bytes(h)
+
+
+def dfilter_fields(h, in_ptr, nfields, parity_ptr, out_ptr, ws_ptr, ws_bytes, stream):
+    _check(lib.dfilter_fields(h, in_ptr, nfields, parity_ptr, out_ptr, ws_ptr, ws_bytes, stream), "dfilter_fields")
+
+
+def dfilter_sgs_stress(h, u_ptr, ubar_ptr, tau_ptr, stats_ptr, ws_ptr, ws_bytes, stream):
+    _check(lib.dfilter_sgs_stress(h, u_ptr, ubar_ptr, tau_ptr, stats_ptr, ws_ptr, ws_bytes, stream),
+           "dfilter_sgs_stress")
+
+
+def dfilter_destroy(h):
+    lib.dfilter_destroy(h)
+
+
+class DFilter:
+    """A differential-filter handle with its state on the current device."""
+
+    def __init__(self, nx, ny, nz, lx, lz, y, a=0.1, device="cuda"):
+        self.shape = (int(nx), int(ny), int(nz))
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self._y = np.ascontiguousarray(np.asarray(y, dtype=np.float64))
+        desc = DFilterDesc(int(nx), int(ny), int(nz), float(lx), float(lz),
+                           self._y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(a))
+        nbytes = dfilter_state_bytes(desc)
+        if nbytes == 0:
+            raise ElesError(ELES_EINVAL, "dfilter_state_bytes")
+        self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.h = dfilter_setup(desc, _ptr(self.state), nbytes, _stream())
+        self._ws = torch.empty(0, dtype=torch.uint8, device=self.device)
+
+    @classmethod
+    def from_config(cls, cfg, a=0.1, y=None, device="cuda"):
+        from .synth import ygrid
+        if y is None:
+            y = ygrid(cfg.ny, cfg.ykind, cfg.stretch)
+        return cls(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.lz, y, a, device)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            dfilter_destroy(h)
+            self.h = None
+
+    def _workspace(self, nbytes):
+        if self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _field_check(self, t, n):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device != self.device:
+            raise ValueError("fields must be contiguous float32 tensors on the filter's device")
+        if tuple(t.shape) != (n,) + self.shape:
+            raise ValueError(f"expected shape {(n,) + self.shape}, got {tuple(t.shape)}")
+
+    def filter_fields(self, fields: torch.Tensor, parity: Sequence[int], out: Optional[torch.Tensor] = None):
+        nf = fields.shape[0]
+        self._field_check(fields, nf)
+        if out is None:
+            out = torch.empty_like(fields)
+        self._field_check(out, nf)
+        if len(parity) != nf or any(int(p) not in (1, -1) for p in parity):
+            raise ValueError("one parity (+1 even, -1 odd) per field")
+        par = (ctypes.c_int8 * nf)(*[int(p) for p in parity])
+        ws = self._workspace(dfilter_workspace_bytes(self.h, nf))
+        dfilter_fields(self.h, _ptr(fields), nf, ctypes.cast(par, ctypes.c_void_p), _ptr(out),
+                       _ptr(ws), ws.numel(), _stream())
+        return out
+
+    def sgs_stress(self, u: torch.Tensor, ubar=None, tau=None, stats=True):
+        self._field_check(u, 3)
+        if ubar is None:
+            ubar = torch.empty((3,) + self.shape, dtype=torch.float32, device=self.device)
+        if tau is None:
+            tau = torch.empty((6,) + self.shape, dtype=torch.float32, device=self.device)
+        self._field_check(ubar, 3)
+        self._field_check(tau, 6)
+        st = None
+        if stats is True:
+            st = torch.empty((9, self.shape[1]), dtype=torch.float64, device=self.device)
+        elif isinstance(stats, torch.Tensor):
+            if (stats.dtype != torch.float64 or not stats.is_contiguous() or stats.device != self.device
+                    or tuple(stats.shape) != (9, self.shape[1])):
+                raise ValueError("stats must be a contiguous float64 [9, ny] tensor on the filter's device")
+            st = stats
+        ws = self._workspace(dfilter_sgs_workspace_bytes(self.h))
+        dfilter_sgs_stress(self.h, _ptr(u), _ptr(ubar), _ptr(tau), _ptr(st) if st is not None else None,
+                           _ptr(ws), ws.numel(), _stream())
+        return ubar, tau, st

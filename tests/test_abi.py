@@ -126,3 +126,50 @@ def test_closure_validation_without_device(eles):
     assert eles.lib.closure_infer(None, None, 16, 16, None, 16, 1 << 20, None) == eles.ELES_EINVAL
     assert eles.lib.closure_step(None) == -1
     assert eles.closure_blob_bytes() == 3 * 9414 * 4 + 32 * 8 + 8
+
+
+def _ddesc(eles, nx=16, ny=17, nz=12, lx=2.0, lz=1.0, y=None, a=0.1):
+    if y is None:
+        y = np.cos(np.pi * np.arange(ny)[::-1] / (ny - 1))
+        y[0], y[-1] = -1.0, 1.0
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    d = eles.DFilterDesc(nx, ny, nz, lx, lz, y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a)
+    return d, y
+
+
+def test_dfilter_state_size_and_validation(eles):
+    d, y = _ddesc(eles)
+    n = eles.dfilter_state_bytes(d)
+    # at least the factor tables: 2 (hx+1)(hz+1) ny pivots and inverses in FP32
+    assert n > 2 * 2 * 9 * 7 * 17 * 4
+    h = ctypes.c_void_p()
+    assert eles.lib.dfilter_setup(ctypes.byref(d), None, n, None, ctypes.byref(h)) == eles.ELES_EINVAL
+    assert eles.lib.dfilter_setup(ctypes.byref(d), 0x1003, n, None, ctypes.byref(h)) == eles.ELES_EINVAL
+    assert eles.lib.dfilter_setup(ctypes.byref(d), 0x1000, n - 1, None, ctypes.byref(h)) == eles.ELES_ENOSPACE
+    assert eles.lib.dfilter_setup(ctypes.byref(d), 0x1000, n, None, None) == eles.ELES_EINVAL
+    assert not h.value
+
+
+@pytest.mark.parametrize("over", [
+    dict(nx=1), dict(nz=1), dict(ny=3, y=np.array([-1.0, 0.0, 1.0])), dict(lx=0.0),
+    dict(lz=float("nan")), dict(a=0.0), dict(a=-0.1), dict(a=float("inf")),
+    dict(y=np.linspace(-1, 0.9, 17)), dict(y=np.linspace(1, -1, 17)),
+    dict(y=np.concatenate([[-1.0], np.full(15, 0.0), [1.0]])),
+])
+def test_dfilter_invalid_descriptors_rejected(eles, over):
+    d, y = _ddesc(eles, **over)
+    assert eles.dfilter_state_bytes(d) == 0
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(1 << 20)
+    aligned = (ctypes.addressof(buf) + 255) & ~255
+    assert eles.lib.dfilter_setup(ctypes.byref(d), aligned, 1 << 19, None, ctypes.byref(h)) == eles.ELES_EINVAL
+    assert not h.value
+
+
+def test_dfilter_calls_on_null_handle_rejected(eles):
+    par = (ctypes.c_int8 * 1)(1)
+    assert eles.lib.dfilter_fields(None, 16, 1, ctypes.cast(par, ctypes.c_void_p), 16, 16, 1 << 20,
+                                   None) == eles.ELES_EINVAL
+    assert eles.lib.dfilter_sgs_stress(None, 16, 16, 16, None, 16, 1 << 20, None) == eles.ELES_EINVAL
+    assert eles.lib.dfilter_workspace_bytes(None, 3) == 0
+    assert eles.lib.dfilter_sgs_workspace_bytes(None) == 0
