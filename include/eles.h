@@ -191,7 +191,7 @@ void filter_destroy(eles_filter f);
  * ownership, streams and errors as for the Gaussian filter above.
  * ====================================================================== */
 typedef struct {
-  int32_t nx, ny, nz;     /* nx, nz >= 2; ny >= 4                               */
+  int32_t nx, ny, nz;     /* nx, nz >= 8; 4 <= ny <= 8192; nx ny nz < 2^29      */
   double lx, lz;          /* periodic lengths, > 0                              */
   const double *y;        /* host, ny values, strictly increasing,
                              y[0] = -1 and y[ny-1] = +1 exactly (the walls)     */

@@ -25,29 +25,28 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
   return pa < pb + nb && pb < pa + na;
 }
 
-enum { D_Y, D_D64, D_S64, D_TX, D_ITX, D_TZ, D_ITZ, D_LO, D_CP, D_INV, D_PROF, D_END };
+enum { D_Y, D_D64, D_P64, D_S64, D_FX, D_IX, D_FZ, D_IZ, D_LO, D_CP, D_INV, D_PROF, D_END };
 
 struct DPlan {
-  int qpx, kpx, qpz, kpz, hx, hz;
+  eles::DAxis ax, az;
+  int hx, hz;
   size_t off[D_END];
   size_t bytes;
 };
 
 int32_t plan_d(const eles_dfilter_desc *d, DPlan *p) {
   if (!d || !d->y) return ELES_EINVAL;
-  if (d->nx < 2 || d->nz < 2 || d->ny < 4 || d->ny > 8192) return ELES_EINVAL;
+  if (d->nx < eles::kDMinN || d->nz < eles::kDMinN || d->ny < 4 || d->ny > 8192) return ELES_EINVAL;
   if (!(std::isfinite(d->lx) && d->lx > 0) || !(std::isfinite(d->lz) && d->lz > 0)) return ELES_EINVAL;
   if (!(std::isfinite(d->a) && d->a > 0)) return ELES_EINVAL;
   const double *y = d->y;
   if (y[0] != -1.0 || y[d->ny - 1] != 1.0) return ELES_EINVAL;
   for (int j = 0; j < d->ny; ++j)
     if (!std::isfinite(y[j]) || (j > 0 && !(y[j] > y[j - 1]))) return ELES_EINVAL;
-  // the kernels count grid points, columns and rows in 32-bit integers
-  if ((double)d->nx * d->ny * d->nz > 2147483647.0) return ELES_ENOTSUP;
-  p->qpx = (d->nx + 15) / 16 * 16;
-  p->kpx = (d->nx + 3) / 4 * 4;
-  p->qpz = (d->nz + 15) / 16 * 16;
-  p->kpz = (d->nz + 3) / 4 * 4;
+  // the transforms address one field through 32-bit byte offsets
+  if ((double)d->nx * d->ny * d->nz * 4.0 >= 2147483648.0) return ELES_ENOTSUP;
+  p->ax = eles::daxis(d->nx);
+  p->az = eles::daxis(d->nz);
   p->hx = d->nx / 2;
   p->hz = d->nz / 2;
   const size_t ny = d->ny;
@@ -55,10 +54,11 @@ int32_t plan_d(const eles_dfilter_desc *d, DPlan *p) {
   const size_t sz[D_END] = {ny * 8,
                             6 * ny * 8,
                             3 * ny * 8,
-                            (size_t)p->qpx * p->kpx * 4,
-                            (size_t)p->qpx * p->kpx * 4,
-                            (size_t)p->qpz * p->kpz * 4,
-                            (size_t)p->qpz * p->kpz * 4,
+                            3 * ny * 8,
+                            eles::dtab_fwd_floats(p->ax) * 4,
+                            eles::dtab_inv_floats(p->ax) * 4,
+                            eles::dtab_fwd_floats(p->az) * 4,
+                            eles::dtab_inv_floats(p->az) * 4,
                             2 * ny * 4,
                             nfac * 4,
                             nfac * 4,
@@ -102,20 +102,19 @@ int32_t dfilter_setup(const eles_dfilter_desc *desc, void *state, size_t state_b
   v.nz = desc->nz;
   v.hx = p.hx;
   v.hz = p.hz;
-  v.qpx = p.qpx;
-  v.kpx = p.kpx;
-  v.qpz = p.qpz;
-  v.kpz = p.kpz;
+  v.ax = p.ax;
+  v.az = p.az;
   v.lx = desc->lx;
   v.lz = desc->lz;
   v.a = desc->a;
   v.y64 = (double *)(s + p.off[D_Y]);
   v.d64 = (double *)(s + p.off[D_D64]);
+  v.p64 = (double *)(s + p.off[D_P64]);
   v.scratch64 = (double *)(s + p.off[D_S64]);
-  v.tx = (float *)(s + p.off[D_TX]);
-  v.itx = (float *)(s + p.off[D_ITX]);
-  v.tz = (float *)(s + p.off[D_TZ]);
-  v.itz = (float *)(s + p.off[D_ITZ]);
+  v.fx = (float *)(s + p.off[D_FX]);
+  v.ix = (float *)(s + p.off[D_IX]);
+  v.fz = (float *)(s + p.off[D_FZ]);
+  v.iz = (float *)(s + p.off[D_IZ]);
   v.lo32 = (float *)(s + p.off[D_LO]);
   v.cp = (float *)(s + p.off[D_CP]);
   v.inv = (float *)(s + p.off[D_INV]);
@@ -176,7 +175,7 @@ int32_t dfilter_sgs_stress(eles_dfilter f, const float *u, float *ubar, float *t
   float *w0 = (float *)ws;
   float *w1 = (float *)((char *)ws + fb);
   double *part = (double *)((char *)ws + 2 * fb);
-  if (eles::launch_dsgs(f->v, u, w0, w1, ubar, tau, stream) != hipSuccess) return ELES_EHIP;
+  if (eles::launch_dsgs(f->v, u, w0, w1, ubar, tau, part, stream) != hipSuccess) return ELES_EHIP;
   if (stats) {
     const int nx = f->d.nx, ny = f->d.ny, nz = f->d.nz;
     if (eles::launch_plane_mean(ubar, 3, nx, ny, nz, part, stats, stream) != hipSuccess ||

@@ -204,26 +204,55 @@ hipError_t launch_plane_mean(const float *f, int nq, int nx, int ny, int nz, dou
 hipError_t launch_train_step(const ClosureView &c, const TrainData &d, const TrainWs &w, uint64_t seed, long step,
                              int batch, AdamArgs adam, hipStream_t s);
 
-// Differential filter (k_dfilt.hip): real Fourier transforms along x and z
-// on the matrix cores, tridiagonal solves in y.
-constexpr int kDFields = 12;   // fields filtered for the stress
+// Differential filter (k_dfilt.hip): folded real Fourier transforms along
+// x and z on the matrix cores, tridiagonal solves in y.
+constexpr int kDFields = 9;   // fields filtered for the stress
+constexpr int kDTS = 7;       // forward transform: 16-row coefficient tiles per wave
+constexpr int kDTI = 4;       // inverse transform: 16-node output tiles per wave
+constexpr int kDNT = 2;       // 16-wide data tiles per wave
+// One periodic axis of n nodes in the folded real basis: cosines 0 .. h,
+// sines 1 .. hs; the contraction runs over the index 1 .. h (folded node,
+// or coefficient) in ks steps of four (ks4 groups of four steps), the
+// index-0 term being added separately; qc cosine and qs sine tiles; gf
+// forward and gi inverse tile groups per data tile.
+struct DAxis {
+  int n, h, hs, ks, ks4, qc, qs, gf, gi;
+};
+constexpr int kDMinN = 8;     // fewest nodes of a periodic axis
+inline DAxis daxis(int n) {
+  DAxis a;
+  a.n = n;
+  a.h = n / 2;
+  a.hs = (n - 1) / 2;
+  a.ks = (a.h + 3) / 4;
+  a.ks4 = (a.ks + 3) / 4;
+  a.qc = (a.h + 1 + 15) / 16;
+  a.qs = (a.hs + 15) / 16;
+  a.gf = (a.qc + a.qs + kDTS - 1) / kDTS;
+  a.gi = (a.qc + kDTI - 1) / kDTI;
+  return a;
+}
+// floats of the pre-arranged forward and inverse tables of an axis
+inline size_t dtab_fwd_floats(const DAxis &a) { return (size_t)a.gf * kDTS * a.ks4 * 256; }
+inline size_t dtab_inv_floats(const DAxis &a) { return (size_t)2 * a.gi * kDTI * a.ks4 * 256; }
 struct DView {
   int nx, ny, nz;
   int hx, hz;                   // nx / 2, nz / 2: wavenumber indices 0 .. h
-  int qpx, kpx, qpz, kpz;       // transform matrices [qp][kp]: rows padded to 16, columns to 4
+  DAxis ax, az;
   double lx, lz, a;
   double *y64;                  // [ny]
   double *d64;                  // [even, odd][sub, main, super][ny] second difference
+  double *p64;                  // [3][ny] sub-diagonal, 1/den, c' of the zero-wavenumber even system
   double *scratch64;            // [3][ny]
-  float *tx, *itx, *tz, *itz;   // forward and inverse transforms
+  float *fx, *ix, *fz, *iz;     // forward and inverse tables of x and z
   float *lo32;                  // [2][ny] system sub-diagonal -a^2 sub
-  float *cp, *inv;              // [2][hx + 1][hz + 1][ny] elimination factors
+  float *cp, *inv;              // [2][hx + 1][ny][hz + 1] elimination factors
   float *prof;                  // [3][ny] m, M = F(m), F(m^2) - M^2
 };
 hipError_t launch_dsetup(const DView &v, hipStream_t s);
 hipError_t launch_dfilter(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1, float *out,
                           hipStream_t s);
 hipError_t launch_dsgs(const DView &v, const float *u, float *w0, float *w1, float *ubar, float *tau,
-                       hipStream_t s);
+                       double *part, hipStream_t s);
 
 }  // namespace eles

@@ -6,17 +6,31 @@
 //
 // The operator is diagonal in the real Fourier basis of x and z (cosines
 // and sines of the grid wavenumbers share the eigenvalue -k^2), so a field
-// is transformed along x and along z (dense real transform matrices on the
-// FP32 matrix cores), every (x coefficient, z coefficient) column is then a
-// tridiagonal system in y, solved by elimination with factors built once
-// per grid, and the result is transformed back.
+// is transformed along x and along z, every (x coefficient, z coefficient)
+// column is then a tridiagonal system in y, solved by elimination with
+// factors built once per grid, and the result is transformed back.
 //
-// Stress: u1 is shifted by its plane-mean profile m(y); the twelve fields
-// u1', u2, u3, their six products and m u1', m u2, m u3 are filtered, and
-//   ubar_1 = F(u1') + M,  M = F(m),
-//   tau_11 = F(u1'u1') - F(u1')^2 + 2 (F(m u1') - M F(u1')) + F(m^2) - M^2,
-//   tau_1j = F(u1'u_j) - F(u1') F(u_j) + F(m u_j) - M F(u_j)   (j = 2, 3),
-//   tau_ij = F(u_i u_j) - F(u_i) F(u_j) otherwise,
+// Transforms. Node k and node n - k share cos(2 pi s k / n) and carry
+// opposite sines, so with e_k = x_k + x_{n-k} and o_k = x_k - x_{n-k}
+// (k = 0 .. n/2, index n - k taken mod n) the cosine coefficients are a
+// product with e and the sine coefficients a product with o, each about
+// half the size of the full transform; the inverse is folded the same way
+// (x_k = P_k + Q_k, x_{n-k} = P_k - Q_k with P the cosine and Q the sine
+// sum). The products run on the FP32 matrix cores (16x16x4 MFMA) with the
+// tables pre-arranged in the A-operand lane order, so one 16-byte load
+// gives a lane its table entries of four K steps; the data is the B
+// operand, read straight from memory through buffer loads whose count per
+// K group is fixed, and the next group is fetched while the current one
+// is multiplied.
+//
+// Stress: u1 is shifted by its plane-mean profile m(y); the nine fields
+// u1', u2, u3 and their six products are filtered. Because m depends on y
+// alone, the x/z coefficients of m u_j are m times those of u_j, so the
+// terms the shift leaves are formed in the solve:
+//   F(u1'u_j) + c_j (F(m u_j) - M F(u_j)) = S^-1(p_j + c_j m u_j) - c_j M S^-1(u_j)
+// (hats on the right: coefficients; c_1 = 2, c_2 = c_3 = 1; M = F(m)), and
+//   ubar_1 = F(u1') + M,  tau_11 = [..]_1 - F(u1')^2 + F(m^2) - M^2,
+//   tau_1j = [..]_j - F(u1') F(u_j),  tau_ij = F(u_i u_j) - F(u_i) F(u_j),
 // the expansion of u1 = u1' + m, exact for any profile.
 #include "eles_internal.h"
 
@@ -24,16 +38,23 @@ namespace eles {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int kBufWord3 = 0x00020000;
+constexpr unsigned kOOB = 0x80000000u;   // offset past every range: loads 0, stores dropped
 
 __device__ inline f4 mma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int kQT = 4;   // 16-row output tiles per wave of the transforms
-// interleaved accumulators of a transform sum: K-step s adds into set
-// s % kNA, so each set sums a quarter of the terms and the rounding error
-// grows with about half the sequential one
-constexpr int kNA = 4;
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const float *p, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)p, 0, (int)(bytes < 0x7fffffffu ? bytes : 0x7fffffffu),
+                                           kBufWord3);
+}
+__device__ inline float bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+}
 
 // |wavenumber| index of real-basis coefficient q of an n-point axis:
 // q = 0 .. n/2 are cosines of index q, the rest sines of index q - n/2
@@ -44,38 +65,65 @@ __device__ __host__ inline int widx(int q, int n) {
 
 // ---------------------------------------------------------------- setup
 
-// Forward transform T [qp][kp] (coefficient q from node k) and inverse
-// transform I [qp][kp] (node q from coefficient k), zero-padded:
-//   cosine s: T = w_s cos(2 pi s k / n), w_0 = w_{n/2} = 1/n, else 2/n;
-//   sine s:   T = (2/n) sin(2 pi s k / n);   I is the basis itself.
-__global__ void k_dtrans(int n, int qp, int kp, float *T, float *I) {
-  const int q = blockIdx.x, k = threadIdx.x + blockIdx.y * blockDim.x;
-  if (q >= qp || k >= kp) return;
-  float t = 0.0f, v = 0.0f;
-  if (q < n && k < n) {
-    const int h = n / 2;
-    // forward: row q (coefficient), column k (node)
-    {
-      const bool cosine = q <= h;
-      const int s = cosine ? q : q - h;
-      const long arg = (2L * s * k) % (2L * n);   // angle / pi, times n
-      double sn, cs;
-      sincospi((double)arg / n, &sn, &cs);
-      const double w = (s == 0 || (cosine && 2 * s == n)) ? 1.0 / n : 2.0 / n;
-      t = (float)(cosine ? w * cs : w * sn);
+// K index of table column (g, s4) of lane row j. MID order (data read one
+// value per lane and step): 1 + 4 (4 g + s4) + j. LAST order (a lane reads
+// four consecutive values with one load): 1 + 16 g + 4 j + s4, and the
+// sine coefficients of the inverse from the top, hs - (16 g + 4 j + s4),
+// so that no group holding a valid index reaches past either end of a row.
+__device__ inline int kcol(bool last, int g, int s4, int j) {
+  return last ? 1 + 16 * g + 4 * j + s4 : 1 + 4 * (4 * g + s4) + j;
+}
+
+// Pre-arranged tables of one axis, entry [tile][g][lane][s4] = M[16 tile +
+// lane % 16][kcol(g, s4, lane / 16)], built in FP64 and rounded to FP32.
+// Forward (row = coefficient, column = folded node k = 1 .. h):
+//   cosine s:  w_s cos(2 pi s k / n), halved at k = n/2 (there e_k = 2 x_k),
+//              w_s = 1/n at s = 0 and s = n/2, else 2/n;
+//   sine s+1:  (2/n) sin(2 pi (s+1) k / n).
+// Inverse (row = output node k = 0 .. h, column = coefficient 1 .. h), the P
+// tiles first, then the Q tiles: cos(2 pi k s / n) and sin(2 pi k s / n).
+// The index-0 terms (node x_0 of the forward sums, coefficient C_0 of the
+// inverse) are added by the kernels.
+__global__ void k_dtab(DAxis ax, bool last, float *fwd, float *inv) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per = (long)ax.ks4 * 256;
+  const long nf = (long)ax.gf * kDTS * per, ni = 2L * ax.gi * kDTI * per;
+  if (e >= nf + ni) return;
+  const bool f = e < nf;
+  const long e2 = f ? e : e - nf;
+  const int tile = (int)(e2 / per);
+  const int r = (int)(e2 - (long)tile * per);
+  const int g = r >> 8, lane = (r & 255) >> 2, s4 = r & 3;
+  const int i = lane & 15, j = lane >> 4;
+  const int col = kcol(last, g, s4, j);
+  const int n = ax.n, h = ax.h, hs = ax.hs;
+  double val = 0.0;
+  // angle 2 pi p q / n in units of pi, reduced exactly
+  auto angle = [n](long p, long q) { return (double)((2L * p * q) % (2L * n)) / n; };
+  if (f) {
+    if (tile < ax.qc) {
+      const int q = 16 * tile + i;
+      if (q <= h && col <= h) {
+        const double w = (q == 0 || 2 * q == n) ? 1.0 / n : 2.0 / n;
+        const double half = 2 * col == n ? 0.5 : 1.0;
+        val = w * half * cospi(angle(q, col));
+      }
+    } else if (tile < ax.qc + ax.qs) {
+      const int q = 16 * (tile - ax.qc) + i;
+      if (q < hs && col <= h) val = (2.0 / n) * sinpi(angle(q + 1, col));
     }
-    // inverse: row q (node), column k (coefficient)
-    {
-      const bool cosine = k <= h;
-      const int s = cosine ? k : k - h;
-      const long arg = (2L * s * q) % (2L * n);
-      double sn, cs;
-      sincospi((double)arg / n, &sn, &cs);
-      v = (float)(cosine ? cs : sn);
+  } else {
+    const int np = ax.gi * kDTI;
+    if (tile < np) {
+      const int k = 16 * tile + i;
+      if (k <= h && col <= h) val = cospi(angle(k, col));
+    } else {
+      const int k = 16 * (tile - np) + i;
+      const int sc = last ? hs - (16 * g + 4 * j + s4) : col;
+      if (k <= h && sc >= 1 && sc <= hs) val = sinpi(angle(k, sc));
     }
   }
-  T[(size_t)q * kp + k] = t;
-  I[(size_t)q * kp + k] = v;
+  (f ? fwd : inv)[e2] = (float)val;
 }
 
 // Second difference on the reflected nodes: d64 [parity 0 = even, 1 = odd]
@@ -122,7 +170,9 @@ __global__ void k_dsecond(DView v) {
 
 // Factors of (1 + a^2 (kx^2 + kz^2)) I - a^2 D for every wavenumber pair
 // (sx, sz) and parity: c'_j and 1/den_j of the elimination, and the scaled
-// sub-diagonal -a^2 lo_j (FP64 arithmetic, FP32 storage).
+// sub-diagonal -a^2 lo_j (FP64 arithmetic, FP32 storage, layout
+// [p][sx][y][sz] so that neighbouring z coefficients are adjacent). The
+// zero-wavenumber even system is also kept in FP64 for the mean profile.
 __global__ void k_dfactor(DView v) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long ncol = (long)(v.hx + 1) * (v.hz + 1);
@@ -130,21 +180,33 @@ __global__ void k_dfactor(DView v) {
   const int p = (int)(t / ncol);
   const long col = t - p * ncol;
   const int sx = (int)(col / (v.hz + 1)), sz = (int)(col % (v.hz + 1));
-  const int ny = v.ny;
+  const int ny = v.ny, nzc = v.hz + 1;
   const double a2 = v.a * v.a;
   const double kx = 2.0 * M_PI * sx / v.lx, kz = 2.0 * M_PI * sz / v.lz;
   const double c = 1.0 + a2 * (kx * kx + kz * kz);
   const double *d = v.d64 + (size_t)p * 3 * ny;
   const int j0 = p ? 1 : 0, j1 = p ? ny - 2 : ny - 1;
-  float *cp = v.cp + ((size_t)p * ncol + col) * ny;
-  float *inv = v.inv + ((size_t)p * ncol + col) * ny;
+  const size_t base = ((size_t)p * (v.hx + 1) + sx) * ny * nzc + sz;
+  float *cp = v.cp + base;
+  float *inv = v.inv + base;
+  const bool keep64 = p == 0 && col == 0;
   double cprev = 0.0;
-  for (int j = j0; j <= j1; ++j) {
+  for (int j = 0; j < ny; ++j) {
+    if (j < j0 || j > j1) {
+      cp[(size_t)j * nzc] = 0.0f;
+      inv[(size_t)j * nzc] = 0.0f;
+      continue;
+    }
     const double L = -a2 * d[j], Dg = c - a2 * d[ny + j], U = -a2 * d[2 * ny + j];
     const double den = j == j0 ? Dg : Dg - L * cprev;
     const double cj = U / den;
-    cp[j] = (float)cj;
-    inv[j] = (float)(1.0 / den);
+    cp[(size_t)j * nzc] = (float)cj;
+    inv[(size_t)j * nzc] = (float)(1.0 / den);
+    if (keep64) {
+      v.p64[j] = L;
+      v.p64[ny + j] = 1.0 / den;
+      v.p64[2 * ny + j] = cj;
+    }
     cprev = cj;
   }
   if (col == 0)
@@ -153,195 +215,529 @@ __global__ void k_dfactor(DView v) {
 
 // ---------------------------------------------------------------- per call
 
-// plane mean of u1 in FP64 -> prof[0] = m (FP32)
-__global__ void __launch_bounds__(256) k_dmean(DView v, const float *__restrict__ u1) {
-  __shared__ double red[256];
-  const int j = blockIdx.x;
-  double s = 0.0;
-  const long cnt = (long)v.nx * v.nz;
-  for (long t = threadIdx.x; t < cnt; t += 256) {
-    const long x = t / v.nz, z = t - x * v.nz;
-    s += (double)u1[((size_t)x * v.ny + j) * v.nz + z];
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) v.prof[j] = (float)(red[0] / (double)cnt);
-}
-
-// M = F(m) and F(m^2) - M^2 (the zero-wavenumber even system, FP64)
-__global__ void k_dprof(DView v) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// M = F(m) and F(m^2) - M^2 from the FP64 plane means of u1 in
+// scratch64[0 .. ny) (the zero-wavenumber even system, FP64); m itself is
+// rounded to FP32 once and that value is used everywhere. The block stages
+// m in LDS; one thread runs the elimination.
+__global__ void __launch_bounds__(256) k_dprof(DView v) {
+  extern __shared__ float sm[];   // [ny]
   const int ny = v.ny;
-  const double a2 = v.a * v.a;
-  const double *d = v.d64;   // even
-  double *w = v.scratch64;   // [3][ny]: c', r'(m), r'(m^2)
-  double cprev = 0.0, r1 = 0.0, r2 = 0.0;
-  for (int j = 0; j < ny; ++j) {
-    const double L = -a2 * d[j], Dg = 1.0 - a2 * d[ny + j], U = -a2 * d[2 * ny + j];
-    const double den = j == 0 ? Dg : Dg - L * cprev;
-    const double m = (double)v.prof[j];
-    r1 = ((j == 0 ? m : m - L * r1)) / den;
-    r2 = ((j == 0 ? m * m : m * m - L * r2)) / den;
-    cprev = U / den;
-    w[j] = cprev;
-    w[ny + j] = r1;
-    w[2 * ny + j] = r2;
+  for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+    const float mf = (float)v.scratch64[j];
+    sm[j] = mf;
+    v.prof[j] = mf;
   }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double *__restrict__ L = v.p64, *__restrict__ iv = v.p64 + ny, *__restrict__ cp = v.p64 + 2 * ny;
+  double *__restrict__ r1s = v.scratch64 + ny, *__restrict__ r2s = v.scratch64 + 2 * ny;
+  double r1 = 0.0, r2 = 0.0;
+  for (int j = 0; j < ny; ++j) {
+    const double m = (double)sm[j];
+    r1 = (m - L[j] * r1) * iv[j];
+    r2 = (m * m - L[j] * r2) * iv[j];
+    r1s[j] = r1;
+    r2s[j] = r2;
+  }
+  float *__restrict__ Mo = v.prof + ny, *__restrict__ So = v.prof + 2 * ny;
   double x1 = 0.0, x2 = 0.0;
   for (int j = ny - 1; j >= 0; --j) {
-    x1 = w[ny + j] - (j == ny - 1 ? 0.0 : w[j] * x1);
-    x2 = w[2 * ny + j] - (j == ny - 1 ? 0.0 : w[j] * x2);
-    v.prof[ny + j] = (float)x1;
-    v.prof[2 * ny + j] = (float)(x2 - x1 * x1);
+    x1 = r1s[j] - cp[j] * x1;
+    x2 = r2s[j] - cp[j] * x2;
+    Mo[j] = (float)x1;
+    So[j] = (float)(x2 - x1 * x1);
   }
 }
 
-// the twelve fields of the stress from u and m
-__global__ void k_dprod(DView v, const float *__restrict__ u, size_t n, float *__restrict__ out) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int y = (int)((t / v.nz) % v.ny);
-  const float m = v.prof[y];
-  const float v0 = u[t] - m, v1 = u[n + t], v2 = u[2 * n + t];
-  const float q[kDFields] = {v0, v1, v2, v0 * v0, v0 * v1, v0 * v2, v1 * v1, v1 * v2, v2 * v2, m * v0, m * v1, m * v2};
-#pragma unroll
-  for (int f = 0; f < kDFields; ++f) out[f * n + t] = q[f];
+// Arguments of the transform kernels. MID: fields [nb][n][C] transformed
+// along the middle axis (columns c contiguous, C = ny nz); LAST: R rows of
+// n contiguous values transformed along the row.
+struct DT {
+  const float *tab;
+  const float *in;
+  float *out;
+  const float *prof;   // m(y), products only
+  DAxis ax;
+  int nb;              // MID: fields
+  int ny, nz;          // MID products: y of column c is c / nz
+  long C;              // MID: columns per field
+  long R;              // LAST: rows
+  size_t fs;           // MID: field stride (elements)
+};
+
+// the two factors of stress field b (0 .. 8): u1', u2, u3, then the
+// products u1'u1', u1'u2, u1'u3, u2u2, u2u3, u3u3
+__device__ inline void dfield(int b, int &ca, int &cb) {
+  ca = b < 3 ? b : (b < 6 ? 0 : (b < 8 ? 1 : 2));
+  cb = b < 3 ? b : (b < 6 ? b - 3 : (b == 6 ? 1 : 2));
 }
 
-// out[b][q][c] = sum_k T[q][k] in[b][k][c]  (transform along a middle axis;
-// c contiguous, C columns). One wave: 16 columns x up to kQT 16-row tiles.
-__global__ void __launch_bounds__(256) k_dmat_mid(const float *__restrict__ T, int Q, int K, int kp,
-                                                  const float *__restrict__ in, float *__restrict__ out, int B,
-                                                  long C, size_t bstride) {
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+__device__ inline f4 bload4(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+// Lane addressing of the transform kernels: the value of K index k and data
+// tile t of this lane is at byte offset k * kstride + loff[t] of the
+// descriptor (MID: k is the row of a column; LAST: the position in a row);
+// lanes past the data (lv false) use kOOB.
+struct Lanes {
+  unsigned loff[kDNT];
+  bool lv[kDNT];
+  unsigned kstride;
+};
+
+// Forward transform. A wave: kDNT data tiles (16 columns or rows each) x
+// kDTS coefficient tiles of one tile group. Accumulators start from the
+// node-0 term w_q x_0 of the cosines.
+// PROD: MID only, the field is formed from u (stress fields, shifted u1).
+template <bool LAST, bool PROD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_dfwd(DT a) {
   const int lane = threadIdx.x & 63, i = lane & 15, j = lane >> 4;
   const long w = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const long nct = (C + 15) / 16;
-  const int nqg = (Q + 16 * kQT - 1) / (16 * kQT);
-  const long total = (long)B * nqg * nct;
-  if (w >= total) return;
-  const int b = (int)(w / ((long)nqg * nct));
-  const long r = w - (long)b * nqg * nct;
-  const int qg = (int)(r / nct);
-  const long c0 = (r - (long)qg * nct) * 16;
-  const int q0 = qg * 16 * kQT;
-  const int ntile = min(kQT, (Q - q0 + 15) / 16);
-  const float *src = in + (size_t)b * bstride;
-  const long c = c0 + i;
-  f4 acc[kNA][kQT];
+  const DAxis ax = a.ax;
+  const int n = ax.n, h = ax.h;
+  long ndg;
+  if (LAST)
+    ndg = (a.R + 16 * kDNT - 1) / (16 * kDNT);
+  else
+    ndg = (a.C + 16 * kDNT - 1) / (16 * kDNT) * a.nb;
+  if (w >= ndg * ax.gf) return;
+  const long dg = w / ax.gf;
+  const int tg = (int)(w - dg * ax.gf);
+  const int t0 = tg * kDTS;
+  const int nt = min(kDTS, ax.qc + ax.qs - t0);
+
+  __amdgpu_buffer_rsrc_t sa, sb, dst;
+  Lanes L;
+  float msh[kDNT];    // shift of u1 (products)
+  int ca = 0, cb = 0;
+  int b = 0;
+  if (LAST) {
+    const long r0 = dg * 16 * kDNT;
+    const long rows = min((long)16 * kDNT, a.R - r0);
+    sa = rsrc(a.in + (size_t)r0 * n, (size_t)rows * n * 4);
+    sb = sa;
+    dst = rsrc(a.out + (size_t)r0 * n, (size_t)rows * n * 4);
+    L.kstride = 4;
 #pragma unroll
-  for (int g = 0; g < kNA; ++g)
+    for (int t = 0; t < kDNT; ++t) {
+      L.lv[t] = 16 * t + i < rows;
+      L.loff[t] = (unsigned)((16 * t + i) * n * 4);
+      msh[t] = 0.0f;
+    }
+  } else {
+    const long cg = dg / a.nb;
+    b = (int)(dg - cg * a.nb);
+    const long c0 = cg * 16 * kDNT;
+    const size_t bytes = ((size_t)(n - 1) * a.C + (a.C - c0)) * 4;
+    if (PROD) {
+      dfield(b, ca, cb);
+      sa = rsrc(a.in + (size_t)ca * a.fs + c0, bytes);
+      sb = rsrc(a.in + (size_t)cb * a.fs + c0, bytes);
+    } else {
+      sa = rsrc(a.in + (size_t)b * a.fs + c0, bytes);
+      sb = sa;
+    }
+    dst = rsrc(a.out + (size_t)b * a.fs + c0, bytes);
+    L.kstride = (unsigned)(a.C * 4);
 #pragma unroll
-    for (int t = 0; t < kQT; ++t) acc[g][t] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 4 * kNA) {
-#pragma unroll
-    for (int g = 0; g < kNA; ++g) {
-      const int k = k0 + 4 * g + j;
-      if (k0 + 4 * g >= K) break;
-      const float bv = (k < K && c < C) ? src[(size_t)k * C + c] : 0.0f;
-#pragma unroll
-      for (int t = 0; t < kQT; ++t)
-        if (t < ntile) acc[g][t] = mma(T[(size_t)(q0 + 16 * t + i) * kp + k], bv, acc[g][t]);
+    for (int t = 0; t < kDNT; ++t) {
+      const long c = c0 + 16 * t + i;
+      L.lv[t] = c < a.C;
+      L.loff[t] = (unsigned)((16 * t + i) * 4);
+      msh[t] = 0.0f;
+      if (PROD) {
+        const int y = (int)(min(c, a.C - 1) / a.nz);
+        msh[t] = a.prof[y];
+      }
     }
   }
+  // the field value from the loaded factor(s) (products: shift u1, multiply)
+  auto field = [&](float x, float xb, float sh) __attribute__((always_inline)) {
+    if (!PROD) return x;
+    const float xa = ca == 0 ? x - sh : x;
+    const float xc = cb == 0 ? xb - sh : xb;
+    return b >= 3 ? xa * xc : xa;
+  };
+
+  f4 acc[kDTS][kDNT];
+  {
+    // node 0: cosine q gains w_q x_0
+    float x0[kDNT];
 #pragma unroll
-  for (int t = 0; t < kQT; ++t) acc[0][t] = (acc[0][t] + acc[1][t]) + (acc[2][t] + acc[3][t]);
-  float *dst = out + (size_t)b * bstride;
+    for (int t = 0; t < kDNT; ++t) {
+      const unsigned o = L.lv[t] ? L.loff[t] : kOOB;
+      const float xa = bload(sa, o);
+      const float xb = PROD ? bload(sb, o) : 0.0f;
+      x0[t] = L.lv[t] ? field(xa, xb, msh[t]) : 0.0f;
+    }
 #pragma unroll
-  for (int t = 0; t < kQT; ++t) {
-    if (t >= ntile) break;
+    for (int tt = 0; tt < kDTS; ++tt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int q = 16 * (t0 + tt) + 4 * j + e;
+        const float wq = t0 + tt >= ax.qc ? 0.0f : (q == 0 || 2 * q == n) ? 1.0f / n : 2.0f / n;
+#pragma unroll
+        for (int t = 0; t < kDNT; ++t) acc[tt][t][e] = wq * x0[t];
+      }
+  }
+
+  const float *tab = a.tab + (size_t)t0 * ax.ks4 * 256 + lane * 4;
+  // one group: table operands of four K steps and the data they multiply
+  struct Grp {
+    f4 A[kDTS];
+    float x[4][kDNT], p[4][kDNT], xb[4][kDNT], pb[4][kDNT];
+  };
+  auto load = [&](int g, Grp &G) __attribute__((always_inline)) {
+    const int gc = min(g, ax.ks4 - 1);
+#pragma unroll
+    for (int tt = 0; tt < kDTS; ++tt) G.A[tt] = *(const f4 *)(tab + ((size_t)tt * ax.ks4 + gc) * 256);
+    if (LAST) {
+      // four consecutive nodes k0 .. k0+3 and their partners n-k0-3 .. n-k0
+      const int k0 = 1 + 16 * g + 4 * j;
+#pragma unroll
+      for (int t = 0; t < kDNT; ++t) {
+        const bool ok = L.lv[t] && k0 <= h;
+        const f4 X = bload4(sa, ok ? (unsigned)k0 * 4 + L.loff[t] : kOOB);
+        const f4 P = bload4(sa, ok ? (unsigned)(n - k0 - 3) * 4 + L.loff[t] : kOOB);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          G.x[s4][t] = X[s4];
+          G.p[s4][t] = P[3 - s4];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = 1 + 4 * (4 * g + s4) + j;
+#pragma unroll
+        for (int t = 0; t < kDNT; ++t) {
+          const bool ok = L.lv[t] && k <= h;
+          const unsigned ox = ok ? (unsigned)k * L.kstride + L.loff[t] : kOOB;
+          const unsigned op = ok ? (unsigned)(n - k) * L.kstride + L.loff[t] : kOOB;
+          G.x[s4][t] = bload(sa, ox);
+          G.p[s4][t] = bload(sa, op);
+          if (PROD) {
+            G.xb[s4][t] = bload(sb, ox);
+            G.pb[s4][t] = bload(sb, op);
+          }
+        }
+      }
+    }
+  };
+  auto compute = [&](int g, Grp &G) __attribute__((always_inline)) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      // LAST: a group spans sixteen K indices over lanes and steps; run it whole
+      if (!LAST && 4 * g + s4 >= ax.ks) break;
+      float e[kDNT], o[kDNT];
+#pragma unroll
+      for (int t = 0; t < kDNT; ++t) {
+        float x = G.x[s4][t], p = G.p[s4][t];
+        if (PROD) {
+          // entries past the data read 0 and must stay 0 after the shift
+          const float sh = L.lv[t] && kcol(false, g, s4, j) <= h ? msh[t] : 0.0f;
+          x = field(x, G.xb[s4][t], sh);
+          p = field(p, G.pb[s4][t], sh);
+        }
+        e[t] = x + p;
+        o[t] = x - p;
+      }
+#pragma unroll
+      for (int tt = 0; tt < kDTS; ++tt) {
+        if (tt >= nt) break;
+        const bool cs = t0 + tt < ax.qc;
+#pragma unroll
+        for (int t = 0; t < kDNT; ++t) acc[tt][t] = mma(G.A[tt][s4], cs ? e[t] : o[t], acc[tt][t]);
+      }
+    }
+  };
+  Grp G0, G1;
+  load(0, G0);
+  __builtin_amdgcn_sched_barrier(0);
+  for (int g = 0; g < ax.ks4; g += 2) {
+    load(g + 1, G1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(g, G0);
+    if (g + 1 >= ax.ks4) break;
+    load(g + 2, G0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(g + 1, G1);
+  }
+
+  // coefficient rows: cosine q at q (q <= h), sine q+1 at h + 1 + q (q < hs)
+#pragma unroll
+  for (int tt = 0; tt < kDTS; ++tt) {
+    if (tt >= nt) break;
+    const int tile = t0 + tt;
+    const bool cs = tile < ax.qc;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int q = q0 + 16 * t + 4 * j + e;
-      if (q < Q && c < C) dst[(size_t)q * C + c] = acc[0][t][e];
+      const int q = 16 * (cs ? tile : tile - ax.qc) + 4 * j + e;
+      const bool qv = cs ? q <= h : q < ax.hs;
+      const int row = cs ? q : h + 1 + q;
+#pragma unroll
+      for (int t = 0; t < kDNT; ++t) {
+        const unsigned off = qv && L.lv[t] ? (unsigned)row * L.kstride + L.loff[t] : kOOB;
+        bstore(acc[tt][t][e], dst, off);
+      }
     }
   }
 }
 
-// out[r][q] = sum_k in[r][k] T[q][k]  (transform along the contiguous last
-// axis of R rows). One wave: 16 rows x up to kQT 16-column tiles.
-__global__ void __launch_bounds__(256) k_dmat_last(const float *__restrict__ T, int Q, int K, int kp,
-                                                   const float *__restrict__ in, float *__restrict__ out, long R) {
+// Inverse transform. A wave: kDNT data tiles x kDTI output node tiles,
+// each with a cosine (P) and a sine (Q) accumulator; P starts from the
+// coefficient C_0.
+template <bool LAST>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_dinv(DT a) {
   const int lane = threadIdx.x & 63, i = lane & 15, j = lane >> 4;
   const long w = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int nqg = (Q + 16 * kQT - 1) / (16 * kQT);
-  const long nrt = (R + 15) / 16;
-  if (w >= nrt * nqg) return;
-  const long r0 = (w / nqg) * 16;
-  const int qg = (int)(w % nqg);
-  const int q0 = qg * 16 * kQT;
-  const int ntile = min(kQT, (Q - q0 + 15) / 16);
-  const long r = r0 + i;
-  f4 acc[kNA][kQT];
+  const DAxis ax = a.ax;
+  const int n = ax.n, h = ax.h, hs = ax.hs;
+  long ndg;
+  if (LAST)
+    ndg = (a.R + 16 * kDNT - 1) / (16 * kDNT);
+  else
+    ndg = (a.C + 16 * kDNT - 1) / (16 * kDNT) * a.nb;
+  if (w >= ndg * ax.gi) return;
+  const long dg = w / ax.gi;
+  const int tg = (int)(w - dg * ax.gi);
+  const int t0 = tg * kDTI;
+  const int nt = min(kDTI, ax.qc - t0);
+
+  __amdgpu_buffer_rsrc_t src, dst;
+  Lanes L;
+  if (LAST) {
+    const long r0 = dg * 16 * kDNT;
+    const long rows = min((long)16 * kDNT, a.R - r0);
+    src = rsrc(a.in + (size_t)r0 * n, (size_t)rows * n * 4);
+    dst = rsrc(a.out + (size_t)r0 * n, (size_t)rows * n * 4);
+    L.kstride = 4;
 #pragma unroll
-  for (int g = 0; g < kNA; ++g)
+    for (int t = 0; t < kDNT; ++t) {
+      L.lv[t] = 16 * t + i < rows;
+      L.loff[t] = (unsigned)((16 * t + i) * n * 4);
+    }
+  } else {
+    const long cg = dg / a.nb;
+    const int b = (int)(dg - cg * a.nb);
+    const long c0 = cg * 16 * kDNT;
+    const size_t bytes = ((size_t)(n - 1) * a.C + (a.C - c0)) * 4;
+    src = rsrc(a.in + (size_t)b * a.fs + c0, bytes);
+    dst = rsrc(a.out + (size_t)b * a.fs + c0, bytes);
+    L.kstride = (unsigned)(a.C * 4);
 #pragma unroll
-    for (int t = 0; t < kQT; ++t) acc[g][t] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 4 * kNA) {
-#pragma unroll
-    for (int g = 0; g < kNA; ++g) {
-      const int k = k0 + 4 * g + j;
-      if (k0 + 4 * g >= K) break;
-      const float av = (k < K && r < R) ? in[(size_t)r * K + k] : 0.0f;
-#pragma unroll
-      for (int t = 0; t < kQT; ++t)
-        if (t < ntile) acc[g][t] = mma(av, T[(size_t)(q0 + 16 * t + i) * kp + k], acc[g][t]);
+    for (int t = 0; t < kDNT; ++t) {
+      L.lv[t] = c0 + 16 * t + i < a.C;
+      L.loff[t] = (unsigned)((16 * t + i) * 4);
     }
   }
+
+  f4 P[kDTI][kDNT], Q[kDTI][kDNT];
 #pragma unroll
-  for (int t = 0; t < kQT; ++t) acc[0][t] = (acc[0][t] + acc[1][t]) + (acc[2][t] + acc[3][t]);
+  for (int t = 0; t < kDNT; ++t) {
+    const float c0v = bload(src, L.lv[t] ? L.loff[t] : kOOB);
 #pragma unroll
-  for (int t = 0; t < kQT; ++t) {
-    if (t >= ntile) break;
-    const int q = q0 + 16 * t + i;
+    for (int tt = 0; tt < kDTI; ++tt) {
+      P[tt][t] = f4{c0v, c0v, c0v, c0v};
+      Q[tt][t] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+
+  const int np = ax.gi * kDTI;
+  const float *tp = a.tab + (size_t)t0 * ax.ks4 * 256 + lane * 4;
+  const float *tq = a.tab + (size_t)(np + t0) * ax.ks4 * 256 + lane * 4;
+  struct Grp {
+    f4 AP[kDTI], AQ[kDTI];
+    float c[4][kDNT], s[4][kDNT];
+  };
+  auto load = [&](int g, Grp &G) __attribute__((always_inline)) {
+    const int gc = min(g, ax.ks4 - 1);
+#pragma unroll
+    for (int tt = 0; tt < kDTI; ++tt) {
+      G.AP[tt] = *(const f4 *)(tp + ((size_t)tt * ax.ks4 + gc) * 256);
+      G.AQ[tt] = *(const f4 *)(tq + ((size_t)tt * ax.ks4 + gc) * 256);
+    }
+    if (LAST) {
+      // cosines s0 .. s0+3 upward, sines s1 .. s1-3 downward (row h + s)
+      const int s0 = 1 + 16 * g + 4 * j, s1 = hs - 16 * g - 4 * j;
+#pragma unroll
+      for (int t = 0; t < kDNT; ++t) {
+        const f4 C = bload4(src, L.lv[t] && s0 <= h ? (unsigned)s0 * 4 + L.loff[t] : kOOB);
+        const f4 S = bload4(src, L.lv[t] && s1 >= 1 ? (unsigned)(h + s1 - 3) * 4 + L.loff[t] : kOOB);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          G.c[s4][t] = C[s4];
+          G.s[s4][t] = S[3 - s4];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int s = 1 + 4 * (4 * g + s4) + j;   // cosine s (row s), sine s (row h + s)
+#pragma unroll
+        for (int t = 0; t < kDNT; ++t) {
+          const unsigned oc = L.lv[t] && s <= h ? (unsigned)s * L.kstride + L.loff[t] : kOOB;
+          const unsigned os = L.lv[t] && s <= hs ? (unsigned)(h + s) * L.kstride + L.loff[t] : kOOB;
+          G.c[s4][t] = bload(src, oc);
+          G.s[s4][t] = bload(src, os);
+        }
+      }
+    }
+  };
+  auto compute = [&](int g, Grp &G) __attribute__((always_inline)) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      // LAST: a group spans sixteen K indices over lanes and steps; run it whole
+      if (!LAST && 4 * g + s4 >= ax.ks) break;
+#pragma unroll
+      for (int tt = 0; tt < kDTI; ++tt) {
+        if (tt >= nt) break;
+#pragma unroll
+        for (int t = 0; t < kDNT; ++t) {
+          P[tt][t] = mma(G.AP[tt][s4], G.c[s4][t], P[tt][t]);
+          Q[tt][t] = mma(G.AQ[tt][s4], G.s[s4][t], Q[tt][t]);
+        }
+      }
+    }
+  };
+  Grp G0, G1;
+  load(0, G0);
+  __builtin_amdgcn_sched_barrier(0);
+  for (int g = 0; g < ax.ks4; g += 2) {
+    load(g + 1, G1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(g, G0);
+    if (g + 1 >= ax.ks4) break;
+    load(g + 2, G0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(g + 1, G1);
+  }
+
+  // node k = P + Q, node n - k = P - Q
+#pragma unroll
+  for (int tt = 0; tt < kDTI; ++tt) {
+    if (tt >= nt) break;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const long rr = r0 + 4 * j + e;
-      if (q < Q && rr < R) out[(size_t)rr * Q + q] = acc[0][t][e];
+      const int k = 16 * (t0 + tt) + 4 * j + e;
+#pragma unroll
+      for (int t = 0; t < kDNT; ++t) {
+        const float pv = P[tt][t][e], qv = Q[tt][t][e];
+        const unsigned o1 = L.lv[t] && k <= h ? (unsigned)k * L.kstride + L.loff[t] : kOOB;
+        const unsigned o2 = L.lv[t] && k >= 1 && k <= hs ? (unsigned)(n - k) * L.kstride + L.loff[t] : kOOB;
+        bstore(pv + qv, dst, o1);
+        bstore(pv - qv, dst, o2);
+      }
     }
   }
 }
 
-// Tridiagonal solves in y for every (field, x coefficient, z coefficient)
-// column, in place: data [f][qx][y][qz]; parity of field f from pmask.
-__global__ void __launch_bounds__(256) k_dsolve(DView v, float *__restrict__ d, int nf, unsigned pmask) {
+// Tridiagonal solves in y, out of place: in, out [f][qx][y][qz]. Thread
+// per (system, qx, qz). Plain: system f of parity (pmask >> f) & 1 (1:
+// odd). SGS: six systems over the nine stress fields; systems 0 .. 2 carry
+// field g (u_j) and field 3 + g (u1'u_j) with the shift terms folded in.
+constexpr int kCH = 8;   // y values loaded together
+template <bool SGS>
+__global__ void __launch_bounds__(256) k_dsolve(DView v, const float *__restrict__ in, float *__restrict__ out,
+                                                int nf, unsigned pmask) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long ncolf = (long)v.nx * v.nz;
-  if (t >= nf * ncolf) return;
-  const int f = (int)(t / ncolf);
-  const long col = t - f * ncolf;
-  const int qx = (int)(col / v.nz), qz = (int)(col - (long)qx * v.nz);
-  const int p = (pmask >> f) & 1;   // 1: odd
-  const int ny = v.ny, nz = v.nz;
-  const long ncol = (long)(v.hx + 1) * (v.hz + 1);
-  const long fc = (long)widx(qx, v.nx) * (v.hz + 1) + widx(qz, v.nz);
-  const float *cp = v.cp + ((size_t)p * ncol + fc) * ny;
-  const float *inv = v.inv + ((size_t)p * ncol + fc) * ny;
-  const float *lo = v.lo32 + (size_t)p * ny;
-  float *x = d + ((size_t)f * v.nx + qx) * (size_t)ny * nz + qz;
-  const int j0 = p ? 1 : 0, j1 = p ? ny - 2 : ny - 1;
-  float r = x[(size_t)j0 * nz] * inv[j0];
-  x[(size_t)j0 * nz] = r;
-  for (int j = j0 + 1; j <= j1; ++j) {
-    r = (x[(size_t)j * nz] - lo[j] * r) * inv[j];
-    x[(size_t)j * nz] = r;
+  const int nx = v.nx, ny = v.ny, nz = v.nz;
+  const long ncolf = (long)nx * nz;
+  const int ns = SGS ? 6 : nf;
+  if (t >= ns * ncolf) return;
+  const int g = (int)(t / ncolf);
+  const long col = t - g * ncolf;
+  const int qx = (int)(col / nz), qz = (int)(col - (long)qx * nz);
+  int fa, fb = -1, p;
+  float cj = 0.0f;
+  if (SGS) {
+    fa = g < 3 ? g : g + 3;
+    if (g < 3) fb = g + 3;
+    p = (g == 1 || g == 4) ? 1 : 0;
+    cj = g == 0 ? 2.0f : 1.0f;
+  } else {
+    fa = g;
+    p = (pmask >> g) & 1;
   }
-  for (int j = j1 - 1; j >= j0; --j) {
-    r = x[(size_t)j * nz] - cp[j] * r;
-    x[(size_t)j * nz] = r;
+  const bool two = fb >= 0;
+  const int nzc = v.hz + 1;
+  const size_t fbase = ((size_t)p * (v.hx + 1) + widx(qx, nx)) * ny * nzc + widx(qz, nz);
+  const float *__restrict__ cp = v.cp + fbase;
+  const float *__restrict__ iv = v.inv + fbase;
+  const float *__restrict__ lo = v.lo32 + (size_t)p * ny;
+  const float *__restrict__ m = v.prof;
+  const float *__restrict__ M = v.prof + ny;
+  const size_t fs = (size_t)nx * ny * nz;
+  const size_t cbase = (size_t)qx * ny * nz + qz;
+  const float *__restrict__ xa = in + (size_t)fa * fs + cbase;
+  const float *__restrict__ xb = in + (size_t)(two ? fb : fa) * fs + cbase;
+  float *ya = out + (size_t)fa * fs + cbase;
+  float *yb = out + (size_t)(two ? fb : fa) * fs + cbase;
+  const int j0 = p, j1 = ny - 1 - p;
+  // forward elimination: r_j = (d_j - lo_j r_{j-1}) / den_j (lo_{j0} = 0)
+  float ra = 0.0f, rb = 0.0f;
+  for (int jb = j0; jb <= j1; jb += kCH) {
+    float da[kCH], db[kCH], ivj[kCH], lj[kCH], mj[kCH];
+#pragma unroll
+    for (int c = 0; c < kCH; ++c) {
+      const int jj = min(jb + c, j1);
+      da[c] = xa[(size_t)jj * nz];
+      db[c] = two ? xb[(size_t)jj * nz] : 0.0f;
+      ivj[c] = iv[(size_t)jj * nzc];
+      lj[c] = lo[jj];
+      mj[c] = m[jj];
+    }
+#pragma unroll
+    for (int c = 0; c < kCH; ++c) {
+      if (jb + c > j1) break;
+      const int jj = jb + c;
+      ra = (da[c] - lj[c] * ra) * ivj[c];
+      ya[(size_t)jj * nz] = ra;
+      if (two) {
+        rb = ((db[c] + cj * mj[c] * da[c]) - lj[c] * rb) * ivj[c];
+        yb[(size_t)jj * nz] = rb;
+      }
+    }
+  }
+  // back substitution: x_j = r_j - c'_j x_{j+1} (c'_{j1} = 0)
+  float xa1 = 0.0f, xb1 = 0.0f;
+  for (int jt = j1; jt >= j0; jt -= kCH) {
+    float r1[kCH], r2[kCH], cpj[kCH], Mj[kCH];
+#pragma unroll
+    for (int c = 0; c < kCH; ++c) {
+      const int jj = max(jt - c, j0);
+      r1[c] = ya[(size_t)jj * nz];
+      r2[c] = two ? yb[(size_t)jj * nz] : 0.0f;
+      cpj[c] = cp[(size_t)jj * nzc];
+      Mj[c] = M[jj];
+    }
+#pragma unroll
+    for (int c = 0; c < kCH; ++c) {
+      if (jt - c < j0) break;
+      const int jj = jt - c;
+      xa1 = r1[c] - cpj[c] * xa1;
+      ya[(size_t)jj * nz] = xa1;
+      if (two) {
+        xb1 = r2[c] - cpj[c] * xb1;
+        yb[(size_t)jj * nz] = xb1 - cj * Mj[c] * xa1;
+      }
+    }
   }
   if (p) {
-    x[0] = 0.0f;
-    x[(size_t)(ny - 1) * nz] = 0.0f;
+    ya[0] = 0.0f;
+    ya[(size_t)(ny - 1) * nz] = 0.0f;
+    if (two) {
+      yb[0] = 0.0f;
+      yb[(size_t)(ny - 1) * nz] = 0.0f;
+    }
   }
 }
 
-// ubar and tau from the twelve filtered fields g
-__global__ void k_depi(DView v, const float *__restrict__ g, size_t n, float *__restrict__ ubar,
-                       float *__restrict__ tau) {
+// ubar and tau from the nine filtered fields g
+__global__ void __launch_bounds__(256) k_depi(DView v, const float *__restrict__ g, size_t n,
+                                              float *__restrict__ ubar, float *__restrict__ tau) {
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const int y = (int)((t / v.nz) % v.ny);
@@ -352,9 +748,9 @@ __global__ void k_depi(DView v, const float *__restrict__ g, size_t n, float *__
   ubar[t] = G[0] + M;
   ubar[n + t] = G[1];
   ubar[2 * n + t] = G[2];
-  tau[t] = (G[3] - G[0] * G[0]) + 2.0f * (G[9] - M * G[0]) + S;
-  tau[n + t] = (G[4] - G[0] * G[1]) + (G[10] - M * G[1]);
-  tau[2 * n + t] = (G[5] - G[0] * G[2]) + (G[11] - M * G[2]);
+  tau[t] = (G[3] - G[0] * G[0]) + S;
+  tau[n + t] = G[4] - G[0] * G[1];
+  tau[2 * n + t] = G[5] - G[0] * G[2];
   tau[3 * n + t] = G[6] - G[1] * G[1];
   tau[4 * n + t] = G[7] - G[1] * G[2];
   tau[5 * n + t] = G[8] - G[2] * G[2];
@@ -362,11 +758,57 @@ __global__ void k_depi(DView v, const float *__restrict__ g, size_t n, float *__
 
 unsigned grid_of(long work, int per) { return (unsigned)((work + per - 1) / per); }
 
+DT targs(const DView &v, bool x, const float *tab, const float *in, float *out, int nb) {
+  DT a;
+  a.tab = tab;
+  a.in = in;
+  a.out = out;
+  a.prof = v.prof;
+  a.ax = x ? v.ax : v.az;
+  a.nb = nb;
+  a.ny = v.ny;
+  a.nz = v.nz;
+  a.C = (long)v.ny * v.nz;
+  a.R = (long)nb * v.nx * v.ny;
+  a.fs = (size_t)v.nx * v.ny * v.nz;
+  return a;
+}
+
+long data_groups(const DT &a, bool last) {
+  return last ? (a.R + 16 * kDNT - 1) / (16 * kDNT) : (a.C + 16 * kDNT - 1) / (16 * kDNT) * a.nb;
+}
+
+// the four transforms and the solve: in -> out through w0, w1 (x forward
+// in -> w1, z forward w1 -> w0, solve w0 -> w1, z inverse w1 -> w0, x
+// inverse w0 -> out; out may be w1)
+template <bool SGS>
+hipError_t run_filter(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1, float *out,
+                      hipStream_t s) {
+  const int nb = SGS ? kDFields : nf;
+  DT a = targs(v, true, v.fx, in, w1, nb);
+  if (SGS)
+    k_dfwd<false, true><<<grid_of(data_groups(a, false) * a.ax.gf, 4), 256, 0, s>>>(a);
+  else
+    k_dfwd<false, false><<<grid_of(data_groups(a, false) * a.ax.gf, 4), 256, 0, s>>>(a);
+  a = targs(v, false, v.fz, w1, w0, nb);
+  k_dfwd<true, false><<<grid_of(data_groups(a, true) * a.ax.gf, 4), 256, 0, s>>>(a);
+  const int ns = SGS ? 6 : nf;
+  k_dsolve<SGS><<<grid_of((long)ns * v.nx * v.nz, 256), 256, 0, s>>>(v, w0, w1, nf, pmask);
+  a = targs(v, false, v.iz, w1, w0, nb);
+  k_dinv<true><<<grid_of(data_groups(a, true) * a.ax.gi, 4), 256, 0, s>>>(a);
+  a = targs(v, true, v.ix, w0, out, nb);
+  k_dinv<false><<<grid_of(data_groups(a, false) * a.ax.gi, 4), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_dsetup(const DView &v, hipStream_t s) {
-  k_dtrans<<<dim3(v.qpx, (v.kpx + 255) / 256), 256, 0, s>>>(v.nx, v.qpx, v.kpx, v.tx, v.itx);
-  k_dtrans<<<dim3(v.qpz, (v.kpz + 255) / 256), 256, 0, s>>>(v.nz, v.qpz, v.kpz, v.tz, v.itz);
+  for (int x = 0; x < 2; ++x) {
+    const DAxis &ax = x ? v.ax : v.az;
+    const long ne = (long)dtab_fwd_floats(ax) + (long)dtab_inv_floats(ax);
+    k_dtab<<<grid_of(ne, 256), 256, 0, s>>>(ax, x == 0, x ? v.fx : v.fz, x ? v.ix : v.iz);
+  }
   k_dsecond<<<grid_of(v.ny, 256), 256, 0, s>>>(v);
   const long ncol = 2L * (v.hx + 1) * (v.hz + 1);
   k_dfactor<<<grid_of(ncol, 64), 64, 0, s>>>(v);
@@ -374,35 +816,23 @@ hipError_t launch_dsetup(const DView &v, hipStream_t s) {
 }
 
 // fields [nf][nx][ny][nz] in `in` -> filtered in `out`; w0, w1: workspaces
-// of nf fields; in may equal w0 (it is only read by the first transform)
+// of nf fields, distinct from in and out
 hipError_t launch_dfilter(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1, float *out,
                           hipStream_t s) {
-  const size_t n = (size_t)v.nx * v.ny * v.nz;
-  const long C = (long)v.ny * v.nz;
-  const long nqgx = (v.nx + 16 * kQT - 1) / (16 * kQT), nqgz = (v.nz + 16 * kQT - 1) / (16 * kQT);
-  const long wx = (long)nf * nqgx * ((C + 15) / 16);
-  const long R = (long)nf * v.nx * v.ny;
-  const long wz = ((R + 15) / 16) * nqgz;
-  // x forward: in -> w1, z forward: w1 -> w0 (may be in: in is no longer needed)
-  k_dmat_mid<<<grid_of(wx, 4), 256, 0, s>>>(v.tx, v.nx, v.nx, v.kpx, in, w1, nf, C, n);
-  k_dmat_last<<<grid_of(wz, 4), 256, 0, s>>>(v.tz, v.nz, v.nz, v.kpz, w1, w0, R);
-  k_dsolve<<<grid_of((long)nf * v.nx * v.nz, 256), 256, 0, s>>>(v, w0, nf, pmask);
-  k_dmat_last<<<grid_of(wz, 4), 256, 0, s>>>(v.itz, v.nz, v.nz, v.kpz, w0, w1, R);
-  k_dmat_mid<<<grid_of(wx, 4), 256, 0, s>>>(v.itx, v.nx, v.nx, v.kpx, w1, out, nf, C, n);
-  return hipGetLastError();
+  return run_filter<false>(v, in, nf, pmask, w0, w1, out, s);
 }
 
+// u [3][nx][ny][nz] -> ubar [3], tau [6]; w0, w1: workspaces of nine
+// fields; part: plane-mean scratch of one field
 hipError_t launch_dsgs(const DView &v, const float *u, float *w0, float *w1, float *ubar, float *tau,
-                       hipStream_t s) {
+                       double *part, hipStream_t s) {
   const size_t n = (size_t)v.nx * v.ny * v.nz;
-  k_dmean<<<v.ny, 256, 0, s>>>(v, u);
-  k_dprof<<<1, 64, 0, s>>>(v);
-  k_dprod<<<grid_of((long)n, 256), 256, 0, s>>>(v, u, n, w0);
-  // parities of the twelve fields: u1', u2, u3, products, m u1', m u2, m u3
-  const unsigned odd = (1u << 1) | (1u << 4) | (1u << 7) | (1u << 10);
-  hipError_t e = launch_dfilter(v, w0, kDFields, odd, w0, w1, w0, s);
+  hipError_t e = launch_plane_mean(u, 1, v.nx, v.ny, v.nz, part, v.scratch64, s);
   if (e != hipSuccess) return e;
-  k_depi<<<grid_of((long)n, 256), 256, 0, s>>>(v, w0, n, ubar, tau);
+  k_dprof<<<1, 256, (size_t)v.ny * sizeof(float), s>>>(v);
+  e = run_filter<true>(v, u, kDFields, 0u, w0, w1, w1, s);
+  if (e != hipSuccess) return e;
+  k_depi<<<grid_of((long)n, 256), 256, 0, s>>>(v, w1, n, ubar, tau);
   return hipGetLastError();
 }
 

@@ -240,10 +240,12 @@ class Filter:
         return cls(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.lz, y,
                    cfg.delta_x, cfg.delta_y, cfg.delta_z, tail_tol, ygemm, device)
 
-    def __del__(self):
+    # bound at class creation: module globals may already be gone when an
+    # object is collected at interpreter exit
+    def __del__(self, _destroy=lib.filter_destroy):
         h = getattr(self, "h", None)
         if h:
-            filter_destroy(h)
+            _destroy(h)
             self.h = None
 
     def set_ygemm(self, ygemm):
@@ -423,10 +425,12 @@ class Closure:
                                 n.ctypes.data_as(_P), _stream())
         self._ws = torch.empty(0, dtype=torch.uint8, device=dev)
 
-    def __del__(self):
+    # bound at class creation: module globals may already be gone when an
+    # object is collected at interpreter exit
+    def __del__(self, _destroy=lib.closure_destroy):
         h = getattr(self, "h", None)
         if h:
-            closure_destroy(h)
+            _destroy(h)
             self.h = None
 
     def _workspace(self, nbytes):
@@ -543,10 +547,12 @@ class DFilter:
             y = ygrid(cfg.ny, cfg.ykind, cfg.stretch)
         return cls(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.lz, y, a, device)
 
-    def __del__(self):
+    # bound at class creation: module globals may already be gone when an
+    # object is collected at interpreter exit
+    def __del__(self, _destroy=lib.dfilter_destroy):
         h = getattr(self, "h", None)
         if h:
-            dfilter_destroy(h)
+            _destroy(h)
             self.h = None
 
     def _workspace(self, nbytes):

@@ -151,7 +151,7 @@ def test_dfilter_state_size_and_validation(eles):
 
 
 @pytest.mark.parametrize("over", [
-    dict(nx=1), dict(nz=1), dict(ny=3, y=np.array([-1.0, 0.0, 1.0])), dict(lx=0.0),
+    dict(nx=1), dict(nz=1), dict(nx=7), dict(nz=5), dict(ny=3, y=np.array([-1.0, 0.0, 1.0])), dict(lx=0.0),
     dict(lz=float("nan")), dict(a=0.0), dict(a=-0.1), dict(a=float("inf")),
     dict(y=np.linspace(-1, 0.9, 17)), dict(y=np.linspace(1, -1, 17)),
     dict(y=np.concatenate([[-1.0], np.full(15, 0.0), [1.0]])),

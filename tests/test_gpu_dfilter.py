@@ -41,6 +41,7 @@ def _host(t):
 
 GRIDS = [
     ("tiny", "tiny", dict()),
+    ("min_sizes", "tiny", dict(nx=8, nz=9, ny=6, ykind="tanh", stretch=2.0)),
     ("odd_sizes", "tiny", dict(nx=10, nz=13, ny=21, ykind="tanh", stretch=2.0)),
     ("dns192_small", "dns192", dict(nx=40, nz=36, ny=33)),
 ]
@@ -82,6 +83,7 @@ def _tolerances(u, ops, tau):
 
 SGS = [
     ("tiny", "tiny", dict(), 0),
+    ("min_sizes", "tiny", dict(nx=8, nz=9, ny=6, ykind="tanh", stretch=2.0), 4),
     ("odd_sizes", "tiny", dict(nx=10, nz=13, ny=21, ykind="tanh", stretch=2.0), 1),
     ("dns192_small", "dns192", dict(nx=40, nz=36, ny=33), 2),
     ("dns192", "dns192", dict(), 3),
