@@ -214,9 +214,10 @@ constexpr int kDNT = 2;       // 16-wide data tiles per wave
 // sines 1 .. hs; the contraction runs over the index 1 .. h (folded node,
 // or coefficient) in ks steps of four (ks4 groups of four steps), the
 // index-0 term being added separately; qc cosine and qs sine tiles; gf
-// forward and gi inverse tile groups per data tile.
+// forward tile groups per data tile (gc of them cosine, the rest sine) and
+// gi inverse ones.
 struct DAxis {
-  int n, h, hs, ks, ks4, qc, qs, gf, gi;
+  int n, h, hs, ks, ks4, qc, qs, gf, gc, gi;
 };
 constexpr int kDMinN = 8;     // fewest nodes of a periodic axis
 inline DAxis daxis(int n) {
@@ -228,7 +229,8 @@ inline DAxis daxis(int n) {
   a.ks4 = (a.ks + 3) / 4;
   a.qc = (a.h + 1 + 15) / 16;
   a.qs = (a.hs + 15) / 16;
-  a.gf = (a.qc + a.qs + kDTS - 1) / kDTS;
+  a.gc = (a.qc + kDTS - 1) / kDTS;
+  a.gf = a.gc + (a.qs + kDTS - 1) / kDTS;
   a.gi = (a.qc + kDTI - 1) / kDTI;
   return a;
 }

@@ -76,12 +76,14 @@ __device__ inline int kcol(bool last, int g, int s4, int j) {
 
 // Pre-arranged tables of one axis, entry [tile][g][lane][s4] = M[16 tile +
 // lane % 16][kcol(g, s4, lane / 16)], built in FP64 and rounded to FP32.
-// Forward (row = coefficient, column = folded node k = 1 .. h):
+// Forward (row = coefficient, column = folded node k = 1 .. h), in groups of
+// kDTS tiles, the cosine groups first, then the sine groups:
 //   cosine s:  w_s cos(2 pi s k / n), halved at k = n/2 (there e_k = 2 x_k),
 //              w_s = 1/n at s = 0 and s = n/2, else 2/n;
 //   sine s+1:  (2/n) sin(2 pi (s+1) k / n).
-// Inverse (row = output node k = 0 .. h, column = coefficient 1 .. h), the P
-// tiles first, then the Q tiles: cos(2 pi k s / n) and sin(2 pi k s / n).
+// Inverse (row = output node k = 0 .. h, column = coefficient 1 .. h), per
+// tile group its P tiles, then its Q tiles: cos(2 pi k s / n) and
+// sin(2 pi k s / n).
 // The index-0 terms (node x_0 of the forward sums, coefficient C_0 of the
 // inverse) are added by the kernels.
 __global__ void k_dtab(DAxis ax, bool last, float *fwd, float *inv) {
@@ -101,24 +103,29 @@ __global__ void k_dtab(DAxis ax, bool last, float *fwd, float *inv) {
   // angle 2 pi p q / n in units of pi, reduced exactly
   auto angle = [n](long p, long q) { return (double)((2L * p * q) % (2L * n)) / n; };
   if (f) {
-    if (tile < ax.qc) {
-      const int q = 16 * tile + i;
+    // tile group tg < gc holds cosine tiles tg kDTS + r, the others sine tiles
+    const int tg = tile / kDTS, r = tile - tg * kDTS;
+    const int ct = tg < ax.gc ? tg * kDTS + r : ax.qc;                // cosine tile, or none
+    const int st = tg < ax.gc ? ax.qs : (tg - ax.gc) * kDTS + r;      // sine tile, or none
+    if (ct < ax.qc) {
+      const int q = 16 * ct + i;
       if (q <= h && col <= h) {
         const double w = (q == 0 || 2 * q == n) ? 1.0 / n : 2.0 / n;
         const double half = 2 * col == n ? 0.5 : 1.0;
         val = w * half * cospi(angle(q, col));
       }
-    } else if (tile < ax.qc + ax.qs) {
-      const int q = 16 * (tile - ax.qc) + i;
+    } else if (st < ax.qs) {
+      const int q = 16 * st + i;
       if (q < hs && col <= h) val = (2.0 / n) * sinpi(angle(q + 1, col));
     }
   } else {
-    const int np = ax.gi * kDTI;
-    if (tile < np) {
-      const int k = 16 * tile + i;
+    // tile group tg holds its kDTI P tiles, then its kDTI Q tiles
+    const int tg = tile / (2 * kDTI), r = tile - tg * 2 * kDTI;
+    if (r < kDTI) {
+      const int k = 16 * (tg * kDTI + r) + i;
       if (k <= h && col <= h) val = cospi(angle(k, col));
     } else {
-      const int k = 16 * (tile - np) + i;
+      const int k = 16 * (tg * kDTI + r - kDTI) + i;
       const int sc = last ? hs - (16 * g + 4 * j + s4) : col;
       if (k <= h && sc >= 1 && sc <= hs) val = sinpi(angle(k, sc));
     }
@@ -273,8 +280,16 @@ __device__ inline void dfield(int b, int &ca, int &cb) {
 }
 
 typedef unsigned u4 __attribute__((ext_vector_type(4)));
+__device__ inline void bstore4(f4 v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off, 0, 0);
+}
 __device__ inline f4 bload4(__amdgpu_buffer_rsrc_t r, unsigned off) {
   return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+// table operand: lane offset in a VGPR, tile/group offset in an SGPR
+__device__ inline f4 tload(__amdgpu_buffer_rsrc_t r, unsigned lane_off, int soff) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, soff, 0));
 }
 
 // Lane addressing of the transform kernels: the value of K index k and data
@@ -287,120 +302,138 @@ struct Lanes {
   unsigned kstride;
 };
 
-// Forward transform. A wave: kDNT data tiles (16 columns or rows each) x
-// kDTS coefficient tiles of one tile group. Accumulators start from the
-// node-0 term w_q x_0 of the cosines.
-// PROD: MID only, the field is formed from u (stress fields, shifted u1).
-template <bool LAST, bool PROD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_dfwd(DT a) {
-  const int lane = threadIdx.x & 63, i = lane & 15, j = lane >> 4;
-  const long w = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const DAxis ax = a.ax;
-  const int n = ax.n, h = ax.h;
-  long ndg;
-  if (LAST)
-    ndg = (a.R + 16 * kDNT - 1) / (16 * kDNT);
-  else
-    ndg = (a.C + 16 * kDNT - 1) / (16 * kDNT) * a.nb;
-  if (w >= ndg * ax.gf) return;
-  const long dg = w / ax.gf;
-  const int tg = (int)(w - dg * ax.gf);
-  const int t0 = tg * kDTS;
-  const int nt = min(kDTS, ax.qc + ax.qs - t0);
-
+// What a wave needs of one data group: descriptors of its input (sa; sb
+// the second factor of a product) and output, and the lane addressing.
+struct Ctx {
   __amdgpu_buffer_rsrc_t sa, sb, dst;
   Lanes L;
-  float msh[kDNT];    // shift of u1 (products)
-  int ca = 0, cb = 0;
-  int b = 0;
+  int b, ca, cb;   // MID: field; products: its factors
+};
+
+template <bool LAST, bool PROD>
+__device__ __attribute__((always_inline)) inline void make_ctx(const DT &a, long dg, Ctx &c) {
+  const int i = threadIdx.x & 15;
+  const int n = a.ax.n;
+  c.b = c.ca = c.cb = 0;
   if (LAST) {
     const long r0 = dg * 16 * kDNT;
     const long rows = min((long)16 * kDNT, a.R - r0);
-    sa = rsrc(a.in + (size_t)r0 * n, (size_t)rows * n * 4);
-    sb = sa;
-    dst = rsrc(a.out + (size_t)r0 * n, (size_t)rows * n * 4);
-    L.kstride = 4;
+    c.sa = rsrc(a.in + (size_t)r0 * n, (size_t)rows * n * 4);
+    c.sb = c.sa;
+    c.dst = rsrc(a.out + (size_t)r0 * n, (size_t)rows * n * 4);
+    c.L.kstride = 4;
 #pragma unroll
     for (int t = 0; t < kDNT; ++t) {
-      L.lv[t] = 16 * t + i < rows;
-      L.loff[t] = (unsigned)((16 * t + i) * n * 4);
-      msh[t] = 0.0f;
+      c.L.lv[t] = 16 * t + i < rows;
+      c.L.loff[t] = (unsigned)((16 * t + i) * n * 4);
     }
   } else {
     const long cg = dg / a.nb;
-    b = (int)(dg - cg * a.nb);
+    c.b = (int)(dg - cg * a.nb);
     const long c0 = cg * 16 * kDNT;
     const size_t bytes = ((size_t)(n - 1) * a.C + (a.C - c0)) * 4;
     if (PROD) {
-      dfield(b, ca, cb);
-      sa = rsrc(a.in + (size_t)ca * a.fs + c0, bytes);
-      sb = rsrc(a.in + (size_t)cb * a.fs + c0, bytes);
+      dfield(c.b, c.ca, c.cb);
+      c.sa = rsrc(a.in + (size_t)c.ca * a.fs + c0, bytes);
+      c.sb = rsrc(a.in + (size_t)c.cb * a.fs + c0, bytes);
     } else {
-      sa = rsrc(a.in + (size_t)b * a.fs + c0, bytes);
-      sb = sa;
+      c.sa = rsrc(a.in + (size_t)c.b * a.fs + c0, bytes);
+      c.sb = c.sa;
     }
-    dst = rsrc(a.out + (size_t)b * a.fs + c0, bytes);
-    L.kstride = (unsigned)(a.C * 4);
+    c.dst = rsrc(a.out + (size_t)c.b * a.fs + c0, bytes);
+    c.L.kstride = (unsigned)(a.C * 4);
 #pragma unroll
     for (int t = 0; t < kDNT; ++t) {
-      const long c = c0 + 16 * t + i;
-      L.lv[t] = c < a.C;
-      L.loff[t] = (unsigned)((16 * t + i) * 4);
-      msh[t] = 0.0f;
-      if (PROD) {
-        const int y = (int)(min(c, a.C - 1) / a.nz);
-        msh[t] = a.prof[y];
-      }
+      c.L.lv[t] = c0 + 16 * t + i < a.C;
+      c.L.loff[t] = (unsigned)((16 * t + i) * 4);
     }
   }
+}
+
+// A wave streams through nd data groups d0, d0 + dstep, ..: the K groups
+// of all of them form one sequence, and the loads of the next K group
+// (possibly the first of the next data group) are issued before the
+// current one is multiplied and, at a data group's end, before its stores
+// (stores share the memory counter with loads).
+template <class Grp, class LoadF, class CompF>
+__device__ __attribute__((always_inline)) inline void stream(long nz, LoadF &load, CompF &compute) {
+  Grp G0, G1;
+  load(G0);
+  __builtin_amdgcn_sched_barrier(0);
+  for (long z = 0; z < nz; z += 2) {
+    load(G1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(G0);
+    if (z + 1 >= nz) break;
+    load(G0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(G1);
+  }
+}
+
+// Forward transform. Per data group: kDNT data tiles (16 columns or rows
+// each) x kDTS coefficient tiles of tile group tg; accumulators start from
+// the node-0 term w_q x_0 of the cosines.
+// PROD: MID only, the field is formed from u (stress fields, shifted u1).
+template <bool LAST, bool PROD, class Tab>
+__device__ __attribute__((always_inline)) inline void fwd_stream(const DT &a, long d0, long dstep, long nd, int tg,
+                                                                 const Tab &T) {
+  const int lane = threadIdx.x & 63, j = lane >> 4;
+  const DAxis ax = a.ax;
+  const int n = ax.n, h = ax.h, ks4 = ax.ks4;
+  const bool cs = tg < ax.gc;   // cosine group (sums x_k + x_{n-k}), else sine group (differences)
+  const int tb = cs ? tg * kDTS : (tg - ax.gc) * kDTS;   // first tile of the group in its half
+  const int nt = min(kDTS, (cs ? ax.qc : ax.qs) - tb);
+  const float sg = cs ? 1.0f : -1.0f;
+  const long nz = nd * ks4;
+
   // the field value from the loaded factor(s) (products: shift u1, multiply)
-  auto field = [&](float x, float xb, float sh) __attribute__((always_inline)) {
+  auto field = [&](const Ctx &c, float x, float xb, float sh) __attribute__((always_inline)) {
     if (!PROD) return x;
-    const float xa = ca == 0 ? x - sh : x;
-    const float xc = cb == 0 ? xb - sh : xb;
-    return b >= 3 ? xa * xc : xa;
+    const float xa = c.ca == 0 ? x - sh : x;
+    const float xc = c.cb == 0 ? xb - sh : xb;
+    return c.b >= 3 ? xa * xc : xa;
   };
 
+  struct Grp {
+    f4 A[Tab::kPre ? kDTS : 1];
+    float x[4][kDNT], p[4][kDNT], xb[4][kDNT], pb[4][kDNT];
+    float x0[kDNT], x0b[kDNT], msh[kDNT];
+  };
+  Ctx cl, cc;   // load and multiply cursors
+  long kl = 0, kc = 0;
+  int gl = 0, gcur = 0;
+  make_ctx<LAST, PROD>(a, d0, cl);
+  cc = cl;
   f4 acc[kDTS][kDNT];
-  {
-    // node 0: cosine q gains w_q x_0
-    float x0[kDNT];
+
+  auto load = [&](Grp &G) __attribute__((always_inline)) {
+    const bool live = kl < nd;
+    const Ctx &c = cl;
+    if constexpr (Tab::kPre) {
 #pragma unroll
-    for (int t = 0; t < kDNT; ++t) {
-      const unsigned o = L.lv[t] ? L.loff[t] : kOOB;
-      const float xa = bload(sa, o);
-      const float xb = PROD ? bload(sb, o) : 0.0f;
-      x0[t] = L.lv[t] ? field(xa, xb, msh[t]) : 0.0f;
+      for (int tt = 0; tt < kDTS; ++tt) G.A[tt] = T.get(tt * ks4 + gl);
     }
 #pragma unroll
-    for (int tt = 0; tt < kDTS; ++tt)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int q = 16 * (t0 + tt) + 4 * j + e;
-        const float wq = t0 + tt >= ax.qc ? 0.0f : (q == 0 || 2 * q == n) ? 1.0f / n : 2.0f / n;
-#pragma unroll
-        for (int t = 0; t < kDNT; ++t) acc[tt][t][e] = wq * x0[t];
+    for (int t = 0; t < kDNT; ++t) {
+      const unsigned o0 = live && c.L.lv[t] ? c.L.loff[t] : kOOB;
+      G.x0[t] = bload(c.sa, o0);
+      G.x0b[t] = PROD ? bload(c.sb, o0) : 0.0f;
+      G.msh[t] = 0.0f;
+      if (PROD) {
+        // shift m(y) of this lane's column (MID: column c = y nz + z)
+        const long col = (long)(c.L.loff[t] / 4) + (long)((kl < nd ? d0 + kl * dstep : d0) / a.nb) * 16 * kDNT;
+        G.msh[t] = a.prof[(int)(min(col, a.C - 1) / a.nz)];
       }
-  }
-
-  const float *tab = a.tab + (size_t)t0 * ax.ks4 * 256 + lane * 4;
-  // one group: table operands of four K steps and the data they multiply
-  struct Grp {
-    f4 A[kDTS];
-    float x[4][kDNT], p[4][kDNT], xb[4][kDNT], pb[4][kDNT];
-  };
-  auto load = [&](int g, Grp &G) __attribute__((always_inline)) {
-    const int gc = min(g, ax.ks4 - 1);
-#pragma unroll
-    for (int tt = 0; tt < kDTS; ++tt) G.A[tt] = *(const f4 *)(tab + ((size_t)tt * ax.ks4 + gc) * 256);
+    }
     if (LAST) {
       // four consecutive nodes k0 .. k0+3 and their partners n-k0-3 .. n-k0
-      const int k0 = 1 + 16 * g + 4 * j;
+      const int k0 = 1 + 16 * gl + 4 * j;
 #pragma unroll
       for (int t = 0; t < kDNT; ++t) {
-        const bool ok = L.lv[t] && k0 <= h;
-        const f4 X = bload4(sa, ok ? (unsigned)k0 * 4 + L.loff[t] : kOOB);
-        const f4 P = bload4(sa, ok ? (unsigned)(n - k0 - 3) * 4 + L.loff[t] : kOOB);
+        const bool ok = live && c.L.lv[t] && k0 <= h;
+        const f4 X = bload4(c.sa, ok ? (unsigned)k0 * 4 + c.L.loff[t] : kOOB);
+        const f4 P = bload4(c.sa, ok ? (unsigned)(n - k0 - 3) * 4 + c.L.loff[t] : kOOB);
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
           G.x[s4][t] = X[s4];
@@ -410,162 +443,157 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     } else {
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
-        const int k = 1 + 4 * (4 * g + s4) + j;
+        const int k = 1 + 4 * (4 * gl + s4) + j;
 #pragma unroll
         for (int t = 0; t < kDNT; ++t) {
-          const bool ok = L.lv[t] && k <= h;
-          const unsigned ox = ok ? (unsigned)k * L.kstride + L.loff[t] : kOOB;
-          const unsigned op = ok ? (unsigned)(n - k) * L.kstride + L.loff[t] : kOOB;
-          G.x[s4][t] = bload(sa, ox);
-          G.p[s4][t] = bload(sa, op);
+          const bool ok = live && c.L.lv[t] && k <= h;
+          const unsigned ox = ok ? (unsigned)k * c.L.kstride + c.L.loff[t] : kOOB;
+          const unsigned op = ok ? (unsigned)(n - k) * c.L.kstride + c.L.loff[t] : kOOB;
+          G.x[s4][t] = bload(c.sa, ox);
+          G.p[s4][t] = bload(c.sa, op);
           if (PROD) {
-            G.xb[s4][t] = bload(sb, ox);
-            G.pb[s4][t] = bload(sb, op);
+            G.xb[s4][t] = bload(c.sb, ox);
+            G.pb[s4][t] = bload(c.sb, op);
           }
         }
       }
     }
+    if (++gl == ks4) {
+      gl = 0;
+      ++kl;
+      if (kl < nd) make_ctx<LAST, PROD>(a, d0 + kl * dstep, cl);
+    }
   };
-  auto compute = [&](int g, Grp &G) __attribute__((always_inline)) {
+
+  auto compute = [&](Grp &G) __attribute__((always_inline)) {
+    const Ctx &c = cc;
+    const int g = gcur;
+    if (g == 0) {
+      // node 0: cosine q gains w_q x_0
+#pragma unroll
+      for (int t = 0; t < kDNT; ++t) {
+        const float x0 = c.L.lv[t] ? field(c, G.x0[t], G.x0b[t], G.msh[t]) : 0.0f;
+#pragma unroll
+        for (int tt = 0; tt < kDTS; ++tt)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int q = 16 * (tb + tt) + 4 * j + e;
+            const float wq = !cs || q > h ? 0.0f : (q == 0 || 2 * q == n) ? 1.0f / n : 2.0f / n;
+            acc[tt][t][e] = wq * x0;
+          }
+      }
+    }
+    f4 A[kDTS];
+#pragma unroll
+    for (int tt = 0; tt < kDTS; ++tt) {
+      if constexpr (Tab::kPre)
+        A[tt] = G.A[tt];
+      else
+        A[tt] = T.get(tt * ks4 + g);
+    }
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       // LAST: a group spans sixteen K indices over lanes and steps; run it whole
       if (!LAST && 4 * g + s4 >= ax.ks) break;
-      float e[kDNT], o[kDNT];
+      float bv[kDNT];   // e_k (cosine group) or o_k (sine group)
 #pragma unroll
       for (int t = 0; t < kDNT; ++t) {
         float x = G.x[s4][t], p = G.p[s4][t];
         if (PROD) {
           // entries past the data read 0 and must stay 0 after the shift
-          const float sh = L.lv[t] && kcol(false, g, s4, j) <= h ? msh[t] : 0.0f;
-          x = field(x, G.xb[s4][t], sh);
-          p = field(p, G.pb[s4][t], sh);
+          const float sh = c.L.lv[t] && kcol(false, g, s4, j) <= h ? G.msh[t] : 0.0f;
+          x = field(c, x, G.xb[s4][t], sh);
+          p = field(c, p, G.pb[s4][t], sh);
         }
-        e[t] = x + p;
-        o[t] = x - p;
+        bv[t] = fmaf(sg, p, x);
       }
 #pragma unroll
       for (int tt = 0; tt < kDTS; ++tt) {
         if (tt >= nt) break;
-        const bool cs = t0 + tt < ax.qc;
 #pragma unroll
-        for (int t = 0; t < kDNT; ++t) acc[tt][t] = mma(G.A[tt][s4], cs ? e[t] : o[t], acc[tt][t]);
+        for (int t = 0; t < kDNT; ++t) acc[tt][t] = mma(A[tt][s4], bv[t], acc[tt][t]);
       }
+    }
+    if (g == ks4 - 1) {
+      // coefficient rows: cosine q at q (q <= h), sine q+1 at h + 1 + q (q < hs)
+      const int qend = cs ? h + 1 : ax.hs;   // valid q < qend
+      const int rb = cs ? 0 : h + 1;
+#pragma unroll
+      for (int tt = 0; tt < kDTS; ++tt) {
+        if (tt >= nt) break;
+        const int q0 = 16 * (tb + tt) + 4 * j;
+        if (LAST && 16 * (tb + tt) + 16 <= qend) {
+          // LAST, whole tile valid: a lane's four outputs are adjacent
+#pragma unroll
+          for (int t = 0; t < kDNT; ++t)
+            bstore4(acc[tt][t], c.dst, c.L.lv[t] ? (unsigned)(rb + q0) * 4 + c.L.loff[t] : kOOB);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int q = q0 + e;
+#pragma unroll
+            for (int t = 0; t < kDNT; ++t) {
+              const unsigned off = q < qend && c.L.lv[t] ? (unsigned)(rb + q) * c.L.kstride + c.L.loff[t] : kOOB;
+              bstore(acc[tt][t][e], c.dst, off);
+            }
+          }
+        }
+      }
+    }
+    if (++gcur == ks4) {
+      gcur = 0;
+      ++kc;
+      if (kc < nd) make_ctx<LAST, PROD>(a, d0 + kc * dstep, cc);
     }
   };
-  Grp G0, G1;
-  load(0, G0);
-  __builtin_amdgcn_sched_barrier(0);
-  for (int g = 0; g < ax.ks4; g += 2) {
-    load(g + 1, G1);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(g, G0);
-    if (g + 1 >= ax.ks4) break;
-    load(g + 2, G0);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(g + 1, G1);
-  }
-
-  // coefficient rows: cosine q at q (q <= h), sine q+1 at h + 1 + q (q < hs)
-#pragma unroll
-  for (int tt = 0; tt < kDTS; ++tt) {
-    if (tt >= nt) break;
-    const int tile = t0 + tt;
-    const bool cs = tile < ax.qc;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int q = 16 * (cs ? tile : tile - ax.qc) + 4 * j + e;
-      const bool qv = cs ? q <= h : q < ax.hs;
-      const int row = cs ? q : h + 1 + q;
-#pragma unroll
-      for (int t = 0; t < kDNT; ++t) {
-        const unsigned off = qv && L.lv[t] ? (unsigned)row * L.kstride + L.loff[t] : kOOB;
-        bstore(acc[tt][t][e], dst, off);
-      }
-    }
-  }
+  stream<Grp>(nz, load, compute);
 }
 
-// Inverse transform. A wave: kDNT data tiles x kDTI output node tiles,
-// each with a cosine (P) and a sine (Q) accumulator; P starts from the
-// coefficient C_0.
-template <bool LAST>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_dinv(DT a) {
-  const int lane = threadIdx.x & 63, i = lane & 15, j = lane >> 4;
-  const long w = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+// Inverse transform. Per data group: kDNT data tiles x kDTI output node
+// tiles, each with a cosine (P) and a sine (Q) accumulator; P starts from
+// the coefficient C_0.
+template <bool LAST, class Tab>
+__device__ __attribute__((always_inline)) inline void inv_stream(const DT &a, long d0, long dstep, long nd, int tg,
+                                                                 const Tab &T) {
+  const int lane = threadIdx.x & 63, j = lane >> 4;
   const DAxis ax = a.ax;
-  const int n = ax.n, h = ax.h, hs = ax.hs;
-  long ndg;
-  if (LAST)
-    ndg = (a.R + 16 * kDNT - 1) / (16 * kDNT);
-  else
-    ndg = (a.C + 16 * kDNT - 1) / (16 * kDNT) * a.nb;
-  if (w >= ndg * ax.gi) return;
-  const long dg = w / ax.gi;
-  const int tg = (int)(w - dg * ax.gi);
+  const int n = ax.n, h = ax.h, hs = ax.hs, ks4 = ax.ks4;
   const int t0 = tg * kDTI;
   const int nt = min(kDTI, ax.qc - t0);
+  const long nz = nd * ks4;
 
-  __amdgpu_buffer_rsrc_t src, dst;
-  Lanes L;
-  if (LAST) {
-    const long r0 = dg * 16 * kDNT;
-    const long rows = min((long)16 * kDNT, a.R - r0);
-    src = rsrc(a.in + (size_t)r0 * n, (size_t)rows * n * 4);
-    dst = rsrc(a.out + (size_t)r0 * n, (size_t)rows * n * 4);
-    L.kstride = 4;
-#pragma unroll
-    for (int t = 0; t < kDNT; ++t) {
-      L.lv[t] = 16 * t + i < rows;
-      L.loff[t] = (unsigned)((16 * t + i) * n * 4);
-    }
-  } else {
-    const long cg = dg / a.nb;
-    const int b = (int)(dg - cg * a.nb);
-    const long c0 = cg * 16 * kDNT;
-    const size_t bytes = ((size_t)(n - 1) * a.C + (a.C - c0)) * 4;
-    src = rsrc(a.in + (size_t)b * a.fs + c0, bytes);
-    dst = rsrc(a.out + (size_t)b * a.fs + c0, bytes);
-    L.kstride = (unsigned)(a.C * 4);
-#pragma unroll
-    for (int t = 0; t < kDNT; ++t) {
-      L.lv[t] = c0 + 16 * t + i < a.C;
-      L.loff[t] = (unsigned)((16 * t + i) * 4);
-    }
-  }
-
-  f4 P[kDTI][kDNT], Q[kDTI][kDNT];
-#pragma unroll
-  for (int t = 0; t < kDNT; ++t) {
-    const float c0v = bload(src, L.lv[t] ? L.loff[t] : kOOB);
-#pragma unroll
-    for (int tt = 0; tt < kDTI; ++tt) {
-      P[tt][t] = f4{c0v, c0v, c0v, c0v};
-      Q[tt][t] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-  }
-
-  const int np = ax.gi * kDTI;
-  const float *tp = a.tab + (size_t)t0 * ax.ks4 * 256 + lane * 4;
-  const float *tq = a.tab + (size_t)(np + t0) * ax.ks4 * 256 + lane * 4;
   struct Grp {
-    f4 AP[kDTI], AQ[kDTI];
+    f4 AP[Tab::kPre ? kDTI : 1], AQ[Tab::kPre ? kDTI : 1];
     float c[4][kDNT], s[4][kDNT];
+    float c0[kDNT];
   };
-  auto load = [&](int g, Grp &G) __attribute__((always_inline)) {
-    const int gc = min(g, ax.ks4 - 1);
+  Ctx cl, cc;
+  long kl = 0, kc = 0;
+  int gl = 0, gcur = 0;
+  make_ctx<LAST, false>(a, d0, cl);
+  cc = cl;
+  f4 P[kDTI][kDNT], Q[kDTI][kDNT];
+
+  auto load = [&](Grp &G) __attribute__((always_inline)) {
+    const bool live = kl < nd;
+    const Ctx &c = cl;
+    if constexpr (Tab::kPre) {
 #pragma unroll
-    for (int tt = 0; tt < kDTI; ++tt) {
-      G.AP[tt] = *(const f4 *)(tp + ((size_t)tt * ax.ks4 + gc) * 256);
-      G.AQ[tt] = *(const f4 *)(tq + ((size_t)tt * ax.ks4 + gc) * 256);
+      for (int tt = 0; tt < kDTI; ++tt) {
+        G.AP[tt] = T.get(tt * ks4 + gl);
+        G.AQ[tt] = T.get((kDTI + tt) * ks4 + gl);
+      }
     }
+#pragma unroll
+    for (int t = 0; t < kDNT; ++t) G.c0[t] = bload(c.sa, live && c.L.lv[t] ? c.L.loff[t] : kOOB);
     if (LAST) {
       // cosines s0 .. s0+3 upward, sines s1 .. s1-3 downward (row h + s)
-      const int s0 = 1 + 16 * g + 4 * j, s1 = hs - 16 * g - 4 * j;
+      const int s0 = 1 + 16 * gl + 4 * j, s1 = hs - 16 * gl - 4 * j;
 #pragma unroll
       for (int t = 0; t < kDNT; ++t) {
-        const f4 C = bload4(src, L.lv[t] && s0 <= h ? (unsigned)s0 * 4 + L.loff[t] : kOOB);
-        const f4 S = bload4(src, L.lv[t] && s1 >= 1 ? (unsigned)(h + s1 - 3) * 4 + L.loff[t] : kOOB);
+        const bool ok = live && c.L.lv[t];
+        const f4 C = bload4(c.sa, ok && s0 <= h ? (unsigned)s0 * 4 + c.L.loff[t] : kOOB);
+        const f4 S = bload4(c.sa, ok && s1 >= 1 ? (unsigned)(h + s1 - 3) * 4 + c.L.loff[t] : kOOB);
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
           G.c[s4][t] = C[s4];
@@ -575,18 +603,47 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     } else {
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
-        const int s = 1 + 4 * (4 * g + s4) + j;   // cosine s (row s), sine s (row h + s)
+        const int sidx = 1 + 4 * (4 * gl + s4) + j;   // cosine s (row s), sine s (row h + s)
 #pragma unroll
         for (int t = 0; t < kDNT; ++t) {
-          const unsigned oc = L.lv[t] && s <= h ? (unsigned)s * L.kstride + L.loff[t] : kOOB;
-          const unsigned os = L.lv[t] && s <= hs ? (unsigned)(h + s) * L.kstride + L.loff[t] : kOOB;
-          G.c[s4][t] = bload(src, oc);
-          G.s[s4][t] = bload(src, os);
+          const bool ok = live && c.L.lv[t];
+          const unsigned oc = ok && sidx <= h ? (unsigned)sidx * c.L.kstride + c.L.loff[t] : kOOB;
+          const unsigned os = ok && sidx <= hs ? (unsigned)(h + sidx) * c.L.kstride + c.L.loff[t] : kOOB;
+          G.c[s4][t] = bload(c.sa, oc);
+          G.s[s4][t] = bload(c.sa, os);
         }
       }
     }
+    if (++gl == ks4) {
+      gl = 0;
+      ++kl;
+      if (kl < nd) make_ctx<LAST, false>(a, d0 + kl * dstep, cl);
+    }
   };
-  auto compute = [&](int g, Grp &G) __attribute__((always_inline)) {
+
+  auto compute = [&](Grp &G) __attribute__((always_inline)) {
+    const Ctx &c = cc;
+    const int g = gcur;
+    if (g == 0) {
+#pragma unroll
+      for (int t = 0; t < kDNT; ++t)
+#pragma unroll
+        for (int tt = 0; tt < kDTI; ++tt) {
+          P[tt][t] = f4{G.c0[t], G.c0[t], G.c0[t], G.c0[t]};
+          Q[tt][t] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    f4 AP[kDTI], AQ[kDTI];
+#pragma unroll
+    for (int tt = 0; tt < kDTI; ++tt) {
+      if constexpr (Tab::kPre) {
+        AP[tt] = G.AP[tt];
+        AQ[tt] = G.AQ[tt];
+      } else {
+        AP[tt] = T.get(tt * ks4 + g);
+        AQ[tt] = T.get((kDTI + tt) * ks4 + g);
+      }
+    }
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       // LAST: a group spans sixteen K indices over lanes and steps; run it whole
@@ -596,42 +653,134 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         if (tt >= nt) break;
 #pragma unroll
         for (int t = 0; t < kDNT; ++t) {
-          P[tt][t] = mma(G.AP[tt][s4], G.c[s4][t], P[tt][t]);
-          Q[tt][t] = mma(G.AQ[tt][s4], G.s[s4][t], Q[tt][t]);
+          P[tt][t] = mma(AP[tt][s4], G.c[s4][t], P[tt][t]);
+          Q[tt][t] = mma(AQ[tt][s4], G.s[s4][t], Q[tt][t]);
         }
       }
     }
-  };
-  Grp G0, G1;
-  load(0, G0);
-  __builtin_amdgcn_sched_barrier(0);
-  for (int g = 0; g < ax.ks4; g += 2) {
-    load(g + 1, G1);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(g, G0);
-    if (g + 1 >= ax.ks4) break;
-    load(g + 2, G0);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(g + 1, G1);
-  }
-
-  // node k = P + Q, node n - k = P - Q
+    if (g == ks4 - 1) {
+      // node k = P + Q, node n - k = P - Q
 #pragma unroll
-  for (int tt = 0; tt < kDTI; ++tt) {
-    if (tt >= nt) break;
+      for (int tt = 0; tt < kDTI; ++tt) {
+        if (tt >= nt) break;
+        const int kt = 16 * (t0 + tt);
+        if (LAST && kt >= 1 && kt + 16 <= hs + 1) {
+          // LAST, whole tile valid for both halves: k0 .. k0+3 upward and
+          // n-k0-3 .. n-k0 downward are adjacent
+          const int k0 = kt + 4 * j;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int k = 16 * (t0 + tt) + 4 * j + e;
+          for (int t = 0; t < kDNT; ++t) {
+            const f4 sp = P[tt][t] + Q[tt][t], sm = P[tt][t] - Q[tt][t];
+            bstore4(sp, c.dst, c.L.lv[t] ? (unsigned)k0 * 4 + c.L.loff[t] : kOOB);
+            bstore4(f4{sm[3], sm[2], sm[1], sm[0]}, c.dst,
+                    c.L.lv[t] ? (unsigned)(n - k0 - 3) * 4 + c.L.loff[t] : kOOB);
+          }
+          continue;
+        }
 #pragma unroll
-      for (int t = 0; t < kDNT; ++t) {
-        const float pv = P[tt][t][e], qv = Q[tt][t][e];
-        const unsigned o1 = L.lv[t] && k <= h ? (unsigned)k * L.kstride + L.loff[t] : kOOB;
-        const unsigned o2 = L.lv[t] && k >= 1 && k <= hs ? (unsigned)(n - k) * L.kstride + L.loff[t] : kOOB;
-        bstore(pv + qv, dst, o1);
-        bstore(pv - qv, dst, o2);
+        for (int e = 0; e < 4; ++e) {
+          const int k = 16 * (t0 + tt) + 4 * j + e;
+#pragma unroll
+          for (int t = 0; t < kDNT; ++t) {
+            const float pv = P[tt][t][e], qv = Q[tt][t][e];
+            const unsigned o1 = c.L.lv[t] && k <= h ? (unsigned)k * c.L.kstride + c.L.loff[t] : kOOB;
+            const unsigned o2 =
+                c.L.lv[t] && k >= 1 && k <= hs ? (unsigned)(n - k) * c.L.kstride + c.L.loff[t] : kOOB;
+            bstore(pv + qv, c.dst, o1);
+            bstore(pv - qv, c.dst, o2);
+          }
+        }
       }
     }
-  }
+    if (++gcur == ks4) {
+      gcur = 0;
+      ++kc;
+      if (kc < nd) make_ctx<LAST, false>(a, d0 + kc * dstep, cc);
+    }
+  };
+  stream<Grp>(nz, load, compute);
+}
+
+// Table accessors: the slice of one tile group (forward: kDTS tiles;
+// inverse: kDTI P tiles then kDTI Q tiles), tile-major, 1 KB per (tile, K
+// group); get(tile * ks4 + g) gives this lane's four entries.
+struct TabG {   // from memory through a descriptor: fetched with the data
+  static constexpr bool kPre = true;
+  __amdgpu_buffer_rsrc_t r;
+  unsigned lane_off;
+  __device__ f4 get(int tg) const { return tload(r, lane_off, tg * 1024); }
+};
+struct TabL {   // from LDS: read when the group is multiplied
+  static constexpr bool kPre = false;
+  const float *p;   // slice + lane * 4
+  __device__ f4 get(int tg) const { return *(const f4 *)(p + tg * 256); }
+};
+
+__device__ inline long data_groups(const DT &a, bool last) {
+  return last ? (a.R + 16 * kDNT - 1) / (16 * kDNT) : (a.C + 16 * kDNT - 1) / (16 * kDNT) * a.nb;
+}
+
+// One wave per (data group, tile group), the table read from memory.
+template <bool LAST, bool PROD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_dfwd(DT a) {
+  const long w = (long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int ngr = a.ax.gf;
+  if (w >= data_groups(a, LAST) * ngr) return;
+  const long dg = w / ngr;
+  const int tg = (int)(w - dg * ngr);
+  const TabG T{rsrc(a.tab + (size_t)tg * kDTS * a.ax.ks4 * 256, (size_t)kDTS * a.ax.ks4 * 1024),
+               (unsigned)(threadIdx.x & 63) * 16};
+  fwd_stream<LAST, PROD>(a, dg, 1, 1, tg, T);
+}
+template <bool LAST>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_dinv(DT a) {
+  const long w = (long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int ngr = a.ax.gi;
+  if (w >= data_groups(a, LAST) * ngr) return;
+  const long dg = w / ngr;
+  const int tg = (int)(w - dg * ngr);
+  const TabG T{rsrc(a.tab + (size_t)tg * 2 * kDTI * a.ax.ks4 * 256, (size_t)2 * kDTI * a.ax.ks4 * 1024),
+               (unsigned)(threadIdx.x & 63) * 16};
+  inv_stream<LAST>(a, dg, 1, 1, tg, T);
+}
+
+// Persistent blocks of kDWaves waves, nbt blocks per tile group: the
+// block's table slice is staged in LDS once and its waves walk a
+// contiguous range of data groups.
+constexpr int kDWaves = 8;
+__device__ inline void stage_table(const float *src, int nfloat, float *lds) {
+  const f4 *s4 = (const f4 *)src;
+  f4 *d4 = (f4 *)lds;
+  for (int e = threadIdx.x; e < nfloat / 4; e += blockDim.x) d4[e] = s4[e];
+  __syncthreads();
+}
+template <bool LAST, bool PROD>
+__global__ void __launch_bounds__(64 * kDWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_dfwd_lds(DT a, int nbt) {
+  extern __shared__ float tl[];
+  const int tg = blockIdx.x / nbt, bi = blockIdx.x - tg * nbt;
+  if (tg >= a.ax.gf) return;   // whole block
+  const int nfl = kDTS * a.ax.ks4 * 256;
+  stage_table(a.tab + (size_t)tg * nfl, nfl, tl);
+  const long ndg = data_groups(a, LAST);
+  const long d0 = ndg * bi / nbt, d1 = ndg * (bi + 1) / nbt;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const TabL T{tl + (threadIdx.x & 63) * 4};
+  if (d0 + wave < d1) fwd_stream<LAST, PROD>(a, d0 + wave, kDWaves, (d1 - d0 - wave + kDWaves - 1) / kDWaves, tg, T);
+}
+template <bool LAST>
+__global__ void __launch_bounds__(64 * kDWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_dinv_lds(DT a, int nbt) {
+  extern __shared__ float tl[];
+  const int tg = blockIdx.x / nbt, bi = blockIdx.x - tg * nbt;
+  if (tg >= a.ax.gi) return;   // whole block
+  const int nfl = 2 * kDTI * a.ax.ks4 * 256;
+  stage_table(a.tab + (size_t)tg * nfl, nfl, tl);
+  const long ndg = data_groups(a, LAST);
+  const long d0 = ndg * bi / nbt, d1 = ndg * (bi + 1) / nbt;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const TabL T{tl + (threadIdx.x & 63) * 4};
+  if (d0 + wave < d1) inv_stream<LAST>(a, d0 + wave, kDWaves, (d1 - d0 - wave + kDWaves - 1) / kDWaves, tg, T);
 }
 
 // Tridiagonal solves in y, out of place: in, out [f][qx][y][qz]. Thread
@@ -774,8 +923,35 @@ DT targs(const DView &v, bool x, const float *tab, const float *in, float *out, 
   return a;
 }
 
-long data_groups(const DT &a, bool last) {
+// the LDS-table kernels cover axes whose table slice fits in 64 KB
+constexpr size_t kDLdsMax = 65536;
+size_t fwd_slice_bytes(const DAxis &ax) { return (size_t)kDTS * ax.ks4 * 1024; }
+size_t inv_slice_bytes(const DAxis &ax) { return (size_t)2 * kDTI * ax.ks4 * 1024; }
+long host_data_groups(const DT &a, bool last) {
   return last ? (a.R + 16 * kDNT - 1) / (16 * kDNT) : (a.C + 16 * kDNT - 1) / (16 * kDNT) * a.nb;
+}
+// blocks per tile group of the persistent kernels: one block per CU in all
+int blocks_per_group(int ngroups) { return max(1, 256 / ngroups); }
+
+template <bool LAST, bool PROD>
+void fwd(const DT &a, hipStream_t s) {
+  const size_t lds = fwd_slice_bytes(a.ax);
+  if (lds <= kDLdsMax) {
+    const int nbt = blocks_per_group(a.ax.gf);
+    k_dfwd_lds<LAST, PROD><<<nbt * a.ax.gf, 64 * kDWaves, lds, s>>>(a, nbt);
+  } else {
+    k_dfwd<LAST, PROD><<<grid_of(host_data_groups(a, LAST) * a.ax.gf, 4), 256, 0, s>>>(a);
+  }
+}
+template <bool LAST>
+void inv(const DT &a, hipStream_t s) {
+  const size_t lds = inv_slice_bytes(a.ax);
+  if (lds <= kDLdsMax) {
+    const int nbt = blocks_per_group(a.ax.gi);
+    k_dinv_lds<LAST><<<nbt * a.ax.gi, 64 * kDWaves, lds, s>>>(a, nbt);
+  } else {
+    k_dinv<LAST><<<grid_of(host_data_groups(a, LAST) * a.ax.gi, 4), 256, 0, s>>>(a);
+  }
 }
 
 // the four transforms and the solve: in -> out through w0, w1 (x forward
@@ -785,19 +961,12 @@ template <bool SGS>
 hipError_t run_filter(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1, float *out,
                       hipStream_t s) {
   const int nb = SGS ? kDFields : nf;
-  DT a = targs(v, true, v.fx, in, w1, nb);
-  if (SGS)
-    k_dfwd<false, true><<<grid_of(data_groups(a, false) * a.ax.gf, 4), 256, 0, s>>>(a);
-  else
-    k_dfwd<false, false><<<grid_of(data_groups(a, false) * a.ax.gf, 4), 256, 0, s>>>(a);
-  a = targs(v, false, v.fz, w1, w0, nb);
-  k_dfwd<true, false><<<grid_of(data_groups(a, true) * a.ax.gf, 4), 256, 0, s>>>(a);
+  fwd<false, SGS>(targs(v, true, v.fx, in, w1, nb), s);
+  fwd<true, false>(targs(v, false, v.fz, w1, w0, nb), s);
   const int ns = SGS ? 6 : nf;
   k_dsolve<SGS><<<grid_of((long)ns * v.nx * v.nz, 256), 256, 0, s>>>(v, w0, w1, nf, pmask);
-  a = targs(v, false, v.iz, w1, w0, nb);
-  k_dinv<true><<<grid_of(data_groups(a, true) * a.ax.gi, 4), 256, 0, s>>>(a);
-  a = targs(v, true, v.ix, w0, out, nb);
-  k_dinv<false><<<grid_of(data_groups(a, false) * a.ax.gi, 4), 256, 0, s>>>(a);
+  inv<true>(targs(v, false, v.iz, w1, w0, nb), s);
+  inv<false>(targs(v, true, v.ix, w0, out, nb), s);
   return hipGetLastError();
 }
 

@@ -44,6 +44,9 @@ GRIDS = [
     ("min_sizes", "tiny", dict(nx=8, nz=9, ny=6, ykind="tanh", stretch=2.0)),
     ("odd_sizes", "tiny", dict(nx=10, nz=13, ny=21, ykind="tanh", stretch=2.0)),
     ("dns192_small", "dns192", dict(nx=40, nz=36, ny=33)),
+    # long axes: several cosine tile groups, tables read from memory
+    ("long_x", "tiny", dict(nx=270, nz=12, ny=9, lx=8.0)),
+    ("long_z", "tiny", dict(nx=10, nz=300, ny=7, lz=9.0)),
 ]
 
 
@@ -86,6 +89,7 @@ SGS = [
     ("min_sizes", "tiny", dict(nx=8, nz=9, ny=6, ykind="tanh", stretch=2.0), 4),
     ("odd_sizes", "tiny", dict(nx=10, nz=13, ny=21, ykind="tanh", stretch=2.0), 1),
     ("dns192_small", "dns192", dict(nx=40, nz=36, ny=33), 2),
+    ("long_xz", "tiny", dict(nx=264, nz=290, ny=7, lx=8.0, lz=9.0), 5),
     ("dns192", "dns192", dict(), 3),
 ]
 
