@@ -137,7 +137,7 @@ size_t dfilter_workspace_bytes(eles_dfilter f, int32_t nfields) {
 size_t dfilter_sgs_workspace_bytes(eles_dfilter f) {
   if (!f) return 0;
   return 2 * up256((size_t)eles::kDFields * f->npts * sizeof(float)) +
-         up256((size_t)eles::plane_mean_parts(6, f->d.ny) * sizeof(double));
+         up256((size_t)eles::dsgs_parts(f->v) * sizeof(double));
 }
 
 int32_t dfilter_fields(eles_dfilter f, const float *in, int32_t nfields, const int8_t *parity, float *out,
@@ -175,14 +175,7 @@ int32_t dfilter_sgs_stress(eles_dfilter f, const float *u, float *ubar, float *t
   float *w0 = (float *)ws;
   float *w1 = (float *)((char *)ws + fb);
   double *part = (double *)((char *)ws + 2 * fb);
-  if (eles::launch_dsgs(f->v, u, w0, w1, ubar, tau, part, stream) != hipSuccess) return ELES_EHIP;
-  if (stats) {
-    const int nx = f->d.nx, ny = f->d.ny, nz = f->d.nz;
-    if (eles::launch_plane_mean(ubar, 3, nx, ny, nz, part, stats, stream) != hipSuccess ||
-        eles::launch_plane_mean(tau, 6, nx, ny, nz, part, stats + 3 * ny, stream) != hipSuccess)
-      return ELES_EHIP;
-  }
-  return ELES_OK;
+  return eles::launch_dsgs(f->v, u, w0, w1, ubar, tau, part, stats, stream) == hipSuccess ? ELES_OK : ELES_EHIP;
 }
 
 void dfilter_destroy(eles_dfilter f) { delete f; }

@@ -255,6 +255,7 @@ hipError_t launch_dsetup(const DView &v, hipStream_t s);
 hipError_t launch_dfilter(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1, float *out,
                           hipStream_t s);
 hipError_t launch_dsgs(const DView &v, const float *u, float *w0, float *w1, float *ubar, float *tau,
-                       double *part, hipStream_t s);
+                       double *part, double *stats, hipStream_t s);
+long dsgs_parts(const DView &v);   // doubles of the statistics scratch of launch_dsgs
 
 }  // namespace eles

@@ -222,37 +222,75 @@ __global__ void k_dfactor(DView v) {
 
 // ---------------------------------------------------------------- per call
 
-// M = F(m) and F(m^2) - M^2 from the FP64 plane means of u1 in
-// scratch64[0 .. ny) (the zero-wavenumber even system, FP64); m itself is
-// rounded to FP32 once and that value is used everywhere. The block stages
-// m in LDS; one thread runs the elimination.
+// Shift profile m(y): the mean of u1 over kMeanSlabs evenly spaced x
+// planes of each y (FP64 sums). Any profile leaves the stress exact; this
+// one removes the bulk of u1 before the products are formed.
+__global__ void __launch_bounds__(256) k_dmean(DView v, const float *__restrict__ u1) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, nz = v.nz;
+  const int cnt = kMeanSlabs * nz;
+  double sum = 0.0;
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int sl = e / nz, z = e - sl * nz;
+    const int x = (int)((long)v.nx * sl / kMeanSlabs);
+    sum += (double)u1[((size_t)x * v.ny + j) * nz + z];
+  }
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) v.scratch64[j] = ((red[0] + red[1]) + (red[2] + red[3])) / cnt;
+}
+
+// M = F(m) and F(m^2) - M^2 from m in scratch64[0 .. ny) (the
+// zero-wavenumber even system, FP64); m itself is rounded to FP32 once and
+// that value is used everywhere. One thread runs the elimination; for
+// ny <= kDProfLds the block first stages m and the FP64 factors in LDS and
+// the elimination keeps its intermediate values there (r1 over m, r2 over
+// the sub-diagonal, both read once before being overwritten).
+constexpr int kDProfLds = 2048;
+__device__ inline void dprof_solve(int ny, double *__restrict__ m, double *__restrict__ L,
+                                   const double *__restrict__ iv, const double *__restrict__ cp,
+                                   float *__restrict__ Mo, float *__restrict__ So) {
+  double r1 = 0.0, r2 = 0.0;
+  for (int j = 0; j < ny; ++j) {
+    const double mj = m[j], lj = L[j], ij = iv[j];
+    r1 = (mj - lj * r1) * ij;
+    r2 = (mj * mj - lj * r2) * ij;
+    m[j] = r1;
+    L[j] = r2;
+  }
+  double x1 = 0.0, x2 = 0.0;
+  for (int j = ny - 1; j >= 0; --j) {
+    x1 = m[j] - cp[j] * x1;
+    x2 = L[j] - cp[j] * x2;
+    Mo[j] = (float)x1;
+    So[j] = (float)(x2 - x1 * x1);
+  }
+}
 __global__ void __launch_bounds__(256) k_dprof(DView v) {
-  extern __shared__ float sm[];   // [ny]
+  extern __shared__ double sd[];   // [4][ny]: m, sub-diagonal, 1/den, c'
   const int ny = v.ny;
+  const bool staged = ny <= kDProfLds;
   for (int j = threadIdx.x; j < ny; j += blockDim.x) {
     const float mf = (float)v.scratch64[j];
-    sm[j] = mf;
     v.prof[j] = mf;
+    if (staged) {
+      sd[j] = (double)mf;
+      sd[ny + j] = v.p64[j];
+      sd[2 * ny + j] = v.p64[ny + j];
+      sd[3 * ny + j] = v.p64[2 * ny + j];
+    } else {
+      v.scratch64[j] = (double)mf;   // m as used, in FP64
+    }
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const double *__restrict__ L = v.p64, *__restrict__ iv = v.p64 + ny, *__restrict__ cp = v.p64 + 2 * ny;
-  double *__restrict__ r1s = v.scratch64 + ny, *__restrict__ r2s = v.scratch64 + 2 * ny;
-  double r1 = 0.0, r2 = 0.0;
-  for (int j = 0; j < ny; ++j) {
-    const double m = (double)sm[j];
-    r1 = (m - L[j] * r1) * iv[j];
-    r2 = (m * m - L[j] * r2) * iv[j];
-    r1s[j] = r1;
-    r2s[j] = r2;
-  }
-  float *__restrict__ Mo = v.prof + ny, *__restrict__ So = v.prof + 2 * ny;
-  double x1 = 0.0, x2 = 0.0;
-  for (int j = ny - 1; j >= 0; --j) {
-    x1 = r1s[j] - cp[j] * x1;
-    x2 = r2s[j] - cp[j] * x2;
-    Mo[j] = (float)x1;
-    So[j] = (float)(x2 - x1 * x1);
+  if (staged) {
+    dprof_solve(ny, sd, sd + ny, sd + 2 * ny, sd + 3 * ny, v.prof + ny, v.prof + 2 * ny);
+  } else {
+    // m in scratch64[0 ..), the sub-diagonal copied to scratch64[ny ..)
+    for (int j = 0; j < ny; ++j) v.scratch64[ny + j] = v.p64[j];
+    dprof_solve(ny, v.scratch64, v.scratch64 + ny, v.p64 + ny, v.p64 + 2 * ny, v.prof + ny, v.prof + 2 * ny);
   }
 }
 
@@ -884,25 +922,66 @@ __global__ void __launch_bounds__(256) k_dsolve(DView v, const float *__restrict
   }
 }
 
-// ubar and tau from the nine filtered fields g
-__global__ void __launch_bounds__(256) k_depi(DView v, const float *__restrict__ g, size_t n,
-                                              float *__restrict__ ubar, float *__restrict__ tau) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int y = (int)((t / v.nz) % v.ny);
-  const float M = v.prof[v.ny + y], S = v.prof[2 * v.ny + y];
-  float G[kDFields];
+// ubar and tau from the nine filtered fields g. Block (xc, y): the points
+// of kDXC x planes at wall-normal index y; with part, also the FP64 sums of
+// the nine outputs over those points, part[(q ny + y) nxc + xc].
+constexpr int kDXC = 16;
+__global__ void __launch_bounds__(256) k_depi(DView v, const float *__restrict__ g, float *__restrict__ ubar,
+                                              float *__restrict__ tau, double *__restrict__ part) {
+  __shared__ double red[4][kDFields];
+  const int xc = blockIdx.x, y = blockIdx.y, nxc = gridDim.x;
+  const int nz = v.nz, ny = v.ny;
+  const int x0 = xc * kDXC, x1 = min(v.nx, x0 + kDXC);
+  const size_t n = (size_t)v.nx * ny * nz;
+  const float M = v.prof[ny + y], S = v.prof[2 * ny + y];
+  double sum[kDFields];
 #pragma unroll
-  for (int f = 0; f < kDFields; ++f) G[f] = g[f * n + t];
-  ubar[t] = G[0] + M;
-  ubar[n + t] = G[1];
-  ubar[2 * n + t] = G[2];
-  tau[t] = (G[3] - G[0] * G[0]) + S;
-  tau[n + t] = G[4] - G[0] * G[1];
-  tau[2 * n + t] = G[5] - G[0] * G[2];
-  tau[3 * n + t] = G[6] - G[1] * G[1];
-  tau[4 * n + t] = G[7] - G[1] * G[2];
-  tau[5 * n + t] = G[8] - G[2] * G[2];
+  for (int q = 0; q < kDFields; ++q) sum[q] = 0.0;
+  const int cnt = (x1 - x0) * nz;
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int xo = e / nz, z = e - xo * nz;
+    const size_t t = ((size_t)(x0 + xo) * ny + y) * nz + z;
+    float G[kDFields];
+#pragma unroll
+    for (int f = 0; f < kDFields; ++f) G[f] = g[f * n + t];
+    float o[kDFields];
+    o[0] = G[0] + M;
+    o[1] = G[1];
+    o[2] = G[2];
+    o[3] = (G[3] - G[0] * G[0]) + S;
+    o[4] = G[4] - G[0] * G[1];
+    o[5] = G[5] - G[0] * G[2];
+    o[6] = G[6] - G[1] * G[1];
+    o[7] = G[7] - G[1] * G[2];
+    o[8] = G[8] - G[2] * G[2];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) ubar[q * n + t] = o[q];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) tau[q * n + t] = o[3 + q];
+#pragma unroll
+    for (int q = 0; q < kDFields; ++q) sum[q] += (double)o[q];
+  }
+  if (!part) return;   // uniform over the grid
+#pragma unroll
+  for (int q = 0; q < kDFields; ++q)
+    for (int off = 32; off > 0; off >>= 1) sum[q] += __shfl_xor(sum[q], off);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < kDFields; ++q) red[threadIdx.x >> 6][q] = sum[q];
+  __syncthreads();
+  if (threadIdx.x < kDFields) {
+    const int q = threadIdx.x;
+    part[((size_t)q * ny + y) * nxc + xc] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+  }
+}
+
+// stats[q][y] = (sum over chunks of part) / (nx nz), chunks in order
+__global__ void k_dstat(const double *__restrict__ part, int nqy, int nxc, double inv, double *__restrict__ stats) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nqy) return;
+  double s = 0.0;
+  for (int c = 0; c < nxc; ++c) s += part[(size_t)i * nxc + c];
+  stats[i] = s * inv;
 }
 
 unsigned grid_of(long work, int per) { return (unsigned)((work + per - 1) / per); }
@@ -992,17 +1071,24 @@ hipError_t launch_dfilter(const DView &v, const float *in, int nf, unsigned pmas
 }
 
 // u [3][nx][ny][nz] -> ubar [3], tau [6]; w0, w1: workspaces of nine
-// fields; part: plane-mean scratch of one field
+// fields; part: dsgs_parts doubles; stats: FP64 [9][ny] plane means of
+// ubar and tau, or null
 hipError_t launch_dsgs(const DView &v, const float *u, float *w0, float *w1, float *ubar, float *tau,
-                       double *part, hipStream_t s) {
-  const size_t n = (size_t)v.nx * v.ny * v.nz;
-  hipError_t e = launch_plane_mean(u, 1, v.nx, v.ny, v.nz, part, v.scratch64, s);
+                       double *part, double *stats, hipStream_t s) {
+  k_dmean<<<v.ny, 256, 0, s>>>(v, u);
+  const size_t lds = v.ny <= kDProfLds ? (size_t)4 * v.ny * sizeof(double) : 0;
+  k_dprof<<<1, 256, lds, s>>>(v);
+  hipError_t e = run_filter<true>(v, u, kDFields, 0u, w0, w1, w1, s);
   if (e != hipSuccess) return e;
-  k_dprof<<<1, 256, (size_t)v.ny * sizeof(float), s>>>(v);
-  e = run_filter<true>(v, u, kDFields, 0u, w0, w1, w1, s);
-  if (e != hipSuccess) return e;
-  k_depi<<<grid_of((long)n, 256), 256, 0, s>>>(v, w1, n, ubar, tau);
+  const int nxc = (v.nx + kDXC - 1) / kDXC;
+  k_depi<<<dim3(nxc, v.ny), 256, 0, s>>>(v, w1, ubar, tau, stats ? part : nullptr);
+  if (stats) {
+    const int nqy = kDFields * v.ny;
+    k_dstat<<<grid_of(nqy, 256), 256, 0, s>>>(part, nqy, nxc, 1.0 / ((double)v.nx * v.nz), stats);
+  }
   return hipGetLastError();
 }
+
+long dsgs_parts(const DView &v) { return (long)kDFields * v.ny * ((v.nx + kDXC - 1) / kDXC); }
 
 }  // namespace eles
