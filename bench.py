@@ -1,6 +1,6 @@
 """Throughput of the exact filtered velocity + subgrid stress path on one GPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--filter gaussian|differential]
 
 A step is one exact-stress evaluation (filtered velocity, the six stress
 components and their plane averages) of one 192 x 129 x 192 channel
@@ -37,6 +37,9 @@ def parse():
     p.add_argument("--workload", default="dns192")
     p.add_argument("--ygemm", default="fp32", choices=["fp32", "bf16", "bf16x3"])
     p.add_argument("--tail", type=float, default=1e-8)
+    p.add_argument("--filter", default="gaussian", choices=["gaussian", "differential"],
+                   help="the Gaussian filter of the benchmark configuration, or the paper's own "
+                        "differential filter (1 - a^2 lap) ubar = u, a = 0.1")
     p.add_argument("--xz", default="matrix", choices=["matrix", "vector"],
                    help="x/z pass on the matrix cores (where it covers the grid) or the vector units")
     p.add_argument("--snapshots", type=int, default=4)
@@ -92,6 +95,143 @@ def cpu_baseline(cfg, u_host, budget_s):
             "sample": f"{reps} full {cfg.nx}x{cfg.ny}x{cfg.nz} snapshot(s), FP64 dense sums, {el:.1f} s"}, out
 
 
+def dfilter_pass_model(cfg):
+    """Algorithmic bytes and matrix-core flops per grid point of each pass of
+    the differential-filter stress (nine filtered fields)."""
+    def fwd(n):   # folded forward transform: cosines 0..h and sines 1..hs over nodes 1..h
+        h, hs = n // 2, (n - 1) // 2
+        return 2.0 * h * (h + 1 + hs) / n
+    def inv(n):   # folded inverse: P and Q sums for nodes 0..h over coefficients 1..h / 1..hs
+        h, hs = n // 2, (n - 1) // 2
+        return 2.0 * (h + 1) * (h + hs) / n
+    nf = 9
+    return {
+        "x_fwd": dict(bytes=48.0, flops=nf * fwd(cfg.nx), kernel="dfilter_xf"),   # reads u, writes 9 fields
+        "z_fwd": dict(bytes=72.0, flops=nf * fwd(cfg.nz), kernel="dfilter_zf"),
+        "y_solve": dict(bytes=72.0, flops=0.0, kernel="dfilter_y"),
+        "z_inv": dict(bytes=72.0, flops=nf * inv(cfg.nz), kernel="dfilter_zi"),
+        "x_inv": dict(bytes=72.0, flops=nf * inv(cfg.nx), kernel="dfilter_xi"),
+        "epilogue": dict(bytes=72.0, flops=0.0, kernel="dfilter_epi"),   # 9 fields in, ubar + tau out
+    }
+
+
+def dfilter_cpu_baseline(cfg, u_host, budget_s):
+    """The FP64 differential-filter oracle timed on the host cores."""
+    from threadpoolctl import threadpool_info
+    import numpy as np
+    from oracle import dfilter_ref as D
+    ops = D.DOperators.from_config(cfg)
+    u64 = u_host.astype(np.float64)
+    reps, t0 = 0, time.perf_counter()
+    out = None
+    while True:
+        out = D.sgs_stress(u64, ops)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 64:
+            break
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    return {"value": cfg.points * reps / el, "unit": "points/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{reps} full {cfg.nx}x{cfg.ny}x{cfg.nz} snapshot(s), FP64 FFT + Thomas, {el:.1f} s"}, out
+
+
+def main_differential(a):
+    import numpy as np
+    import torch
+    from paper_1902_02508_amd import counters, eles, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = synth.config(a.workload)
+    seeds = synth.SEEDS.get(a.workload, [0, 1, 2, 3])[: a.snapshots]
+    while len(seeds) < a.snapshots:
+        seeds.append(seeds[-1] + 1)
+    hosts, us = [], []
+    for sd in seeds:
+        y, u = synth.make_snapshot(cfg, sd)
+        hosts.append(u)
+        us.append(torch.from_numpy(u).to(dev))
+    f = eles.DFilter.from_config(cfg, a=0.1, device=dev)
+    ns = len(us)
+    ubar = [torch.empty((3,) + f.shape, dtype=torch.float32, device=dev) for _ in range(ns)]
+    tau = [torch.empty((6,) + f.shape, dtype=torch.float32, device=dev) for _ in range(ns)]
+    stats = [torch.empty((9, cfg.ny), dtype=torch.float64, device=dev) for _ in range(ns)]
+
+    def step(i):
+        k = i % ns
+        f.sgs_stress(us[k], ubar[k], tau[k], stats[k])
+
+    for i in range(a.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    print(f"warmup done ({a.warmup} steps)", file=sys.stderr, flush=True)
+    eles.dfilter_profile_begin(f.h, a.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        step(i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = eles.dfilter_profile_end(f.h)
+    el = t1 - t0
+    ms_per_step = 1e3 * el / a.steps
+    value = cfg.points * a.steps / el
+    print(f"timed {a.steps} steps: {ms_per_step:.4f} ms/step", file=sys.stderr, flush=True)
+
+    model = dfilter_pass_model(cfg)
+    traffic_rec = counters.read_summary(os.path.join(ROOT, "profiles", f"hbm_traffic_{a.workload}_differential.md"))
+    roofs = {}
+    for k, m in model.items():
+        ms, nl = prof[k]
+        t_k = ms / 1e3 / max(nl, 1)
+        gbs = m["bytes"] * cfg.points / t_k / 1e9
+        r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+        if m["flops"] > 0:
+            tfs = m["flops"] * cfg.points / t_k / 1e12
+            if tfs / FP32_MFMA_PEAK_TF >= r["frac"]:
+                r = {"bound": "mfma", "achieved": tfs, "peak": FP32_MFMA_PEAK_TF, "unit": "TFLOP/s",
+                     "frac": tfs / FP32_MFMA_PEAK_TF,
+                     "note": "folded real-transform multiply-adds on FP32 matrix cores; padding of the "
+                             "16x16 tiles and the K steps past n/2 are not counted"}
+        r["kernel"] = m["kernel"]
+        r["us_avg"] = 1e6 * t_k
+        tr = counters.current(traffic_rec, m["kernel"])
+        r["traffic"] = tr["bytes"] if tr else None
+        roofs[k] = r
+    dom = max(model, key=lambda k: prof[k][0])
+    passes = {k: {"us_avg": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in prof.items()}
+
+    cpu = None
+    parity = None
+    if a.cpu_seconds > 0:
+        from oracle import filter_ref as R
+        cpu, (rub, rtau) = dfilter_cpu_baseline(cfg, hosts[0], a.cpu_seconds)
+        f.sgs_stress(us[0], ubar[0], tau[0], stats[0])
+        torch.cuda.synchronize()
+        yv = synth.ygrid(cfg.ny, cfg.ykind, cfg.stretch)
+        gu = ubar[0].cpu().numpy().astype(np.float64)
+        gt = tau[0].cpu().numpy().astype(np.float64)
+        parity = max([R.rel_l2(gu[k], rub[k], yv) for k in range(3)] +
+                     [R.rel_l2(gt[k], rtau[k], yv) for k in range(6)])
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": f"channel {cfg.nx}x{cfg.ny}x{cfg.nz} exact filtered velocity + tau_ij, "
+                               "differential filter",
+                   "filter": "differential", "a": 0.1,
+                   "box": f"{cfg.lx:.4f}x2x{cfg.lz:.4f}", "snapshots": ns, "parallelism": "none"},
+        "roofline": roofs[dom],
+        "rooflines": roofs,
+        "cpu_baseline": cpu,
+        "passes": passes,
+        "max_rel_l2_vs_oracle": parity,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.copy_calibration:
@@ -101,6 +241,9 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
               "(snapshots are independent: run one process per GPU)", file=sys.stderr)
         sys.exit(2)
+    if a.filter == "differential":
+        main_differential(a)
+        return
     import numpy as np
     import torch
     from paper_1902_02508_amd import counters, eles, synth

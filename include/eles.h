@@ -234,6 +234,21 @@ int32_t dfilter_fields(eles_dfilter f, const float *in, int32_t nfields, const i
 int32_t dfilter_sgs_stress(eles_dfilter f, const float *u, float *ubar, float *tau, double *stats, void *ws,
                            size_t ws_bytes, hipStream_t stream);
 
+/* Per-pass GPU timing of later dfilter_sgs_stress / dfilter_fields calls on
+ * this handle, with HIP events recorded on the call's stream around every
+ * pass: 0 shift profile, 1 x forward transform (with the products), 2 z
+ * forward transform, 3 y solves, 4 z inverse transform, 5 x inverse
+ * transform, 6 stress epilogue and plane statistics (dfilter_fields times
+ * passes 1 .. 5). dfilter_profile_begin creates events for up to max_calls
+ * calls (host-side HIP events; no device memory); dfilter_profile_end waits
+ * for the device and returns, per pass, the summed milliseconds and the
+ * number of timed launches, then releases the events. Errors: EINVAL,
+ * EHIP. */
+#define ELES_DNPASS 7
+int32_t dfilter_profile_begin(eles_dfilter f, int32_t max_calls);
+int32_t dfilter_profile_end(eles_dfilter f, double *ms /* [ELES_DNPASS] */,
+                            int32_t *launches /* [ELES_DNPASS] */);
+
 void dfilter_destroy(eles_dfilter f);
 
 /* ======================================================================

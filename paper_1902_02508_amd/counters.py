@@ -25,12 +25,22 @@ import re
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 
-# kernel symbol fragment -> (short name, sources it is compiled from)
+# kernel symbol fragment (name, or name with template arguments) ->
+# (short name, sources it is compiled from)
+_DF = ["k_dfilt.hip", "eles_internal.h"]
 KERNELS = {
     "k_xz": ("k_xz", ["k_xz.hip", "eles_internal.h"]),
     "k_xzm": ("k_xzm", ["k_xzm.hip", "eles_internal.h"]),
     "k_ys": ("k_ys", ["k_ys.hip", "eles_internal.h"]),
+    # differential filter: transforms (x with the products, z), y solves, epilogue
+    "k_dfwd_lds<false, true>": ("dfilter_xf", _DF),
+    "k_dfwd_lds<true, false>": ("dfilter_zf", _DF),
+    "k_dsolve<true>": ("dfilter_y", _DF),
+    "k_dinv_lds<true>": ("dfilter_zi", _DF),
+    "k_dinv_lds<false>": ("dfilter_xi", _DF),
+    "k_depi": ("dfilter_epi", _DF),
 }
+_SOURCES = {name: srcs for name, srcs in KERNELS.values()}
 
 
 def source_hash(names) -> str:
@@ -53,9 +63,12 @@ def _per_dispatch(directory: str, counter: str) -> dict:
             for r in csv.DictReader(fh):
                 if r["Counter_Name"] != counter:
                     continue
-                m = re.search(r"(k_[a-z_0-9]+)", r["Kernel_Name"])
-                key = m.group(1) if m else r["Kernel_Name"]
-                out.setdefault(key, []).append(float(r["Counter_Value"]))
+                # filed under the bare name and, for templates, also with
+                # the template arguments
+                m = re.search(r"(k_[a-z_0-9]+)(<[^>]*>)?", r["Kernel_Name"])
+                keys = [m.group(1)] + ([m.group(1) + m.group(2)] if m.group(2) else []) if m else [r["Kernel_Name"]]
+                for key in keys:
+                    out.setdefault(key, []).append(float(r["Counter_Value"]))
     return out
 
 
@@ -102,7 +115,7 @@ def current(record, name):
     if not record or name not in record.get("kernels", {}):
         return None
     k = record["kernels"][name]
-    if k["source_sha256"] != source_hash(KERNELS[name][1]):
+    if name not in _SOURCES or k["source_sha256"] != source_hash(_SOURCES[name]):
         return None
     return k
 

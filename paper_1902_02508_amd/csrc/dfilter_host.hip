@@ -14,11 +14,35 @@ struct eles_dfilter_s {
   std::vector<double> y;
   eles::DView v;
   size_t npts;
+  // timing: events [call][pass][start, stop], used flags [call][pass]
+  int prof_max = 0, prof_calls = 0;
+  std::vector<hipEvent_t> ev;
+  std::vector<char> used;
 };
 
 namespace {
 
+static_assert(eles::kDPasses == ELES_DNPASS, "pass count");
+
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// events of the next call, marking the passes it times; null when off
+const hipEvent_t *call_events(eles_dfilter_s *f, bool sgs) {
+  if (f->prof_max == 0 || f->prof_calls >= f->prof_max) return nullptr;
+  const size_t base = (size_t)f->prof_calls * ELES_DNPASS;
+  for (int p = 0; p < ELES_DNPASS; ++p)
+    f->used[base + p] = sgs || (p != eles::kDPassShift && p != eles::kDPassEpi);
+  ++f->prof_calls;
+  return f->ev.data() + 2 * base;
+}
+
+void release_events(eles_dfilter_s *f) {
+  for (hipEvent_t e : f->ev)
+    if (e) (void)hipEventDestroy(e);
+  f->ev.clear();
+  f->used.clear();
+  f->prof_max = f->prof_calls = 0;
+}
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 bool overlap(const void *a, size_t na, const void *b, size_t nb) {
   const char *pa = (const char *)a, *pb = (const char *)b;
@@ -155,7 +179,9 @@ int32_t dfilter_fields(eles_dfilter f, const float *in, int32_t nfields, const i
   if (overlap(ws, ws_bytes, in, bytes) || overlap(ws, ws_bytes, out, bytes)) return ELES_EINVAL;
   float *w0 = (float *)ws;
   float *w1 = (float *)((char *)ws + up256(bytes));
-  return eles::launch_dfilter(f->v, in, nfields, pmask, w0, w1, out, stream) == hipSuccess ? ELES_OK : ELES_EHIP;
+  return eles::launch_dfilter(f->v, in, nfields, pmask, w0, w1, out, stream, call_events(f, false)) == hipSuccess
+             ? ELES_OK
+             : ELES_EHIP;
 }
 
 int32_t dfilter_sgs_stress(eles_dfilter f, const float *u, float *ubar, float *tau, double *stats, void *ws,
@@ -175,9 +201,53 @@ int32_t dfilter_sgs_stress(eles_dfilter f, const float *u, float *ubar, float *t
   float *w0 = (float *)ws;
   float *w1 = (float *)((char *)ws + fb);
   double *part = (double *)((char *)ws + 2 * fb);
-  return eles::launch_dsgs(f->v, u, w0, w1, ubar, tau, part, stats, stream) == hipSuccess ? ELES_OK : ELES_EHIP;
+  return eles::launch_dsgs(f->v, u, w0, w1, ubar, tau, part, stats, stream, call_events(f, true)) == hipSuccess
+             ? ELES_OK
+             : ELES_EHIP;
 }
 
-void dfilter_destroy(eles_dfilter f) { delete f; }
+int32_t dfilter_profile_begin(eles_dfilter f, int32_t max_calls) {
+  if (!f || max_calls < 1 || max_calls > (1 << 20)) return ELES_EINVAL;
+  release_events(f);
+  const size_t n = (size_t)max_calls * ELES_DNPASS;
+  f->ev.assign(2 * n, nullptr);
+  f->used.assign(n, 0);
+  for (auto &e : f->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      release_events(f);
+      return ELES_EHIP;
+    }
+  f->prof_max = max_calls;
+  f->prof_calls = 0;
+  return ELES_OK;
+}
+
+int32_t dfilter_profile_end(eles_dfilter f, double *ms, int32_t *launches) {
+  if (!f || !ms || !launches || f->prof_max == 0) return ELES_EINVAL;
+  for (int p = 0; p < ELES_DNPASS; ++p) {
+    ms[p] = 0.0;
+    launches[p] = 0;
+  }
+  int32_t st = ELES_OK;
+  if (hipDeviceSynchronize() != hipSuccess) st = ELES_EHIP;
+  for (size_t k = 0; st == ELES_OK && k < f->used.size(); ++k) {
+    if (!f->used[k]) continue;
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, f->ev[2 * k], f->ev[2 * k + 1]) != hipSuccess) {
+      st = ELES_EHIP;
+      break;
+    }
+    ms[k % ELES_DNPASS] += t;
+    launches[k % ELES_DNPASS] += 1;
+  }
+  release_events(f);
+  return st;
+}
+
+void dfilter_destroy(eles_dfilter f) {
+  if (!f) return;
+  release_events(f);
+  delete f;
+}
 
 }  // extern "C"

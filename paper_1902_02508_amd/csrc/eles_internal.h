@@ -252,10 +252,12 @@ struct DView {
   float *prof;                  // [3][ny] m, M = F(m), F(m^2) - M^2
 };
 hipError_t launch_dsetup(const DView &v, hipStream_t s);
+// timed passes (ev: 2 events per pass, or null)
+enum { kDPassShift, kDPassXf, kDPassZf, kDPassY, kDPassZi, kDPassXi, kDPassEpi, kDPasses };
 hipError_t launch_dfilter(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1, float *out,
-                          hipStream_t s);
+                          hipStream_t s, const hipEvent_t *ev);
 hipError_t launch_dsgs(const DView &v, const float *u, float *w0, float *w1, float *ubar, float *tau,
-                       double *part, double *stats, hipStream_t s);
+                       double *part, double *stats, hipStream_t s, const hipEvent_t *ev);
 long dsgs_parts(const DView &v);   // doubles of the statistics scratch of launch_dsgs
 
 }  // namespace eles

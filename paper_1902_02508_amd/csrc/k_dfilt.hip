@@ -1036,16 +1036,32 @@ void inv(const DT &a, hipStream_t s) {
 // the four transforms and the solve: in -> out through w0, w1 (x forward
 // in -> w1, z forward w1 -> w0, solve w0 -> w1, z inverse w1 -> w0, x
 // inverse w0 -> out; out may be w1)
+// Timing events of one call: ev[2 p] before and ev[2 p + 1] after pass p
+// (DPass), or null.
+void mark(const hipEvent_t *ev, int idx, hipStream_t s) {
+  if (ev) (void)hipEventRecord(ev[idx], s);
+}
+
 template <bool SGS>
 hipError_t run_filter(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1, float *out,
-                      hipStream_t s) {
+                      hipStream_t s, const hipEvent_t *ev) {
   const int nb = SGS ? kDFields : nf;
+  mark(ev, 2 * kDPassXf, s);
   fwd<false, SGS>(targs(v, true, v.fx, in, w1, nb), s);
+  mark(ev, 2 * kDPassXf + 1, s);
+  mark(ev, 2 * kDPassZf, s);
   fwd<true, false>(targs(v, false, v.fz, w1, w0, nb), s);
+  mark(ev, 2 * kDPassZf + 1, s);
   const int ns = SGS ? 6 : nf;
+  mark(ev, 2 * kDPassY, s);
   k_dsolve<SGS><<<grid_of((long)ns * v.nx * v.nz, 256), 256, 0, s>>>(v, w0, w1, nf, pmask);
+  mark(ev, 2 * kDPassY + 1, s);
+  mark(ev, 2 * kDPassZi, s);
   inv<true>(targs(v, false, v.iz, w1, w0, nb), s);
+  mark(ev, 2 * kDPassZi + 1, s);
+  mark(ev, 2 * kDPassXi, s);
   inv<false>(targs(v, true, v.ix, w0, out, nb), s);
+  mark(ev, 2 * kDPassXi + 1, s);
   return hipGetLastError();
 }
 
@@ -1066,26 +1082,30 @@ hipError_t launch_dsetup(const DView &v, hipStream_t s) {
 // fields [nf][nx][ny][nz] in `in` -> filtered in `out`; w0, w1: workspaces
 // of nf fields, distinct from in and out
 hipError_t launch_dfilter(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1, float *out,
-                          hipStream_t s) {
-  return run_filter<false>(v, in, nf, pmask, w0, w1, out, s);
+                          hipStream_t s, const hipEvent_t *ev) {
+  return run_filter<false>(v, in, nf, pmask, w0, w1, out, s, ev);
 }
 
 // u [3][nx][ny][nz] -> ubar [3], tau [6]; w0, w1: workspaces of nine
 // fields; part: dsgs_parts doubles; stats: FP64 [9][ny] plane means of
 // ubar and tau, or null
 hipError_t launch_dsgs(const DView &v, const float *u, float *w0, float *w1, float *ubar, float *tau,
-                       double *part, double *stats, hipStream_t s) {
+                       double *part, double *stats, hipStream_t s, const hipEvent_t *ev) {
+  mark(ev, 2 * kDPassShift, s);
   k_dmean<<<v.ny, 256, 0, s>>>(v, u);
   const size_t lds = v.ny <= kDProfLds ? (size_t)4 * v.ny * sizeof(double) : 0;
   k_dprof<<<1, 256, lds, s>>>(v);
-  hipError_t e = run_filter<true>(v, u, kDFields, 0u, w0, w1, w1, s);
+  mark(ev, 2 * kDPassShift + 1, s);
+  hipError_t e = run_filter<true>(v, u, kDFields, 0u, w0, w1, w1, s, ev);
   if (e != hipSuccess) return e;
   const int nxc = (v.nx + kDXC - 1) / kDXC;
+  mark(ev, 2 * kDPassEpi, s);
   k_depi<<<dim3(nxc, v.ny), 256, 0, s>>>(v, w1, ubar, tau, stats ? part : nullptr);
   if (stats) {
     const int nqy = kDFields * v.ny;
     k_dstat<<<grid_of(nqy, 256), 256, 0, s>>>(part, nqy, nxc, 1.0 / ((double)v.nx * v.nz), stats);
   }
+  mark(ev, 2 * kDPassEpi + 1, s);
   return hipGetLastError();
 }
 

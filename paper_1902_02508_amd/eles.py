@@ -83,6 +83,8 @@ _SIG = {
     "dfilter_fields": (_I, [_P, _P, _I, _P, _P, _P, _S, _P]),
     "dfilter_sgs_stress": (_I, [_P, _P, _P, _P, _P, _P, _S, _P]),
     "dfilter_destroy": (None, [_P]),
+    "dfilter_profile_begin": (_I, [_P, _I]),
+    "dfilter_profile_end": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)]),
     "closure_state_bytes": (_S, []),
     "closure_create": (_I, [_P, _S, _P, _P, _P, ctypes.POINTER(_P)]),
     "closure_step": (ctypes.c_int64, [_P]),
@@ -519,6 +521,22 @@ def dfilter_sgs_stress(h, u_ptr, ubar_ptr, tau_ptr, stats_ptr, ws_ptr, ws_bytes,
 
 def dfilter_destroy(h):
     lib.dfilter_destroy(h)
+
+
+DNPASS = 7
+DPASS_NAMES = ("shift", "x_fwd", "z_fwd", "y_solve", "z_inv", "x_inv", "epilogue")
+
+
+def dfilter_profile_begin(h, max_calls: int):
+    _check(lib.dfilter_profile_begin(h, max_calls), "dfilter_profile_begin")
+
+
+def dfilter_profile_end(h):
+    """{pass name: (summed ms, timed launches)}."""
+    ms = (ctypes.c_double * DNPASS)()
+    n = (_I * DNPASS)()
+    _check(lib.dfilter_profile_end(h, ms, n), "dfilter_profile_end")
+    return {DPASS_NAMES[p]: (ms[p], n[p]) for p in range(DNPASS)}
 
 
 class DFilter:
