@@ -183,3 +183,83 @@ def test_planted_parity_mistake_is_caught():
     f = np.ones((8, ny, 4)) * prof[None, :, None]
     f[:, [0, -1], :] = 0.0
     assert np.max(np.abs(D.dfilt(f, 1, ops) - D.dfilt(f, -1, ops))) > 1e-3
+
+
+@pytest.mark.parametrize("parity", [1, -1])
+def test_inverse_operator_eigenvalues(parity):
+    """The inverse filter (1 - a^2 lap), applied forward, multiplies the
+    eigenfunctions of the reflected difference by 1 + a^2 (kx^2 + kz^2)
+    + a^2 (2/h^2)(1 - cos(n pi h / 2)) on a uniform y grid."""
+    nx, ny, nz, lx, lz, a = 12, 21, 10, 2.0, 1.5, 0.17
+    y = _uniform_y(ny)
+    h = y[1] - y[0]
+    ops = _ops(nx, ny, nz, lx, lz, y, a)
+    x = np.arange(nx) * lx / nx
+    z = np.arange(nz) * lz / nz
+    kx, kz = 2 * math.pi * 3 / lx, 2 * math.pi * 2 / lz
+    kap = 5 * math.pi / 2
+    lam = 1.0 + a * a * (kx * kx + kz * kz) + a * a * (2.0 / h ** 2) * (1.0 - math.cos(kap * h))
+    xz = np.sin(kx * x[:, None, None] + kz * z[None, None, :] - 0.4)
+    prof = np.cos(kap * (y + 1)) if parity > 0 else np.sin(kap * (y + 1))
+    f = xz * prof[None, :, None]
+    if parity < 0:
+        f[:, [0, -1], :] = 0.0
+    assert np.max(np.abs(D.laplacian_apply(f, parity, ops) - lam * f)) < 1e-12
+
+
+@pytest.mark.parametrize("parity", [1, -1])
+def test_inverse_operator_dense(parity):
+    """laplacian_apply equals the dense 3-D operator I - a^2 (Lx + Dy + Lz)
+    of explicit matrix definitions (odd fields: zero rows on the walls)."""
+    nx, ny, nz, lx, lz, a = 6, 9, 5, 2.0, 1.3, 0.21
+    y = synth.ygrid(ny, "tanh", 2.0)
+    ops = _ops(nx, ny, nz, lx, lz, y, a)
+    lxm, lzm, dy = _spectral_d2(nx, lx), _spectral_d2(nz, lz), _fd_matrix(y, parity)
+    ix, iy, iz = np.eye(nx), np.eye(ny), np.eye(nz)
+    lap = np.kron(np.kron(lxm, iy), iz) + np.kron(np.kron(ix, dy), iz) + np.kron(np.kron(ix, iy), lzm)
+    A = np.eye(nx * ny * nz) - a * a * lap
+    f = np.random.default_rng(8).standard_normal((nx, ny, nz))
+    if parity < 0:
+        f[:, [0, -1], :] = 0.0
+    ref = (A @ f.ravel()).reshape(nx, ny, nz)
+    if parity < 0:
+        ref[:, [0, -1], :] = 0.0
+    assert np.max(np.abs(D.laplacian_apply(f, parity, ops) - ref)) < 1e-11
+
+
+# ---- eq. (11) and the eq. (9) extension (a negative test)
+
+def _rms(a):
+    return float(np.sqrt(np.mean(np.asarray(a) ** 2)))
+
+
+def test_eq7_extension_meets_eq11_and_eq9_does_not():
+    """With the eq. (7) parities (u2 odd) the filtered wall-normal velocity
+    vanishes on the walls and the inverse filter returns the no-slip wall
+    values of u1 and u3 (eq. (11)); with the eq. (9) parities (u2 even,
+    u1 and u3 odd) ubar_2 is not zero on the walls, so eq. (11) fails."""
+    cfg = synth.config("tiny", nx=16, nz=12, ny=17)
+    ops = D.DOperators.from_config(cfg)
+    y, u = synth.make_snapshot(cfg, 6)
+    u = u.astype(np.float64)
+    assert np.all(u[:, :, [0, -1], :] == 0.0)          # no-slip input
+    good = [D.dfilt(u[i], p, ops) for i, p in enumerate((1, -1, 1))]
+    assert np.all(good[1][:, [0, -1], :] == 0.0)
+    for i in (0, 2):
+        back = D.laplacian_apply(good[i], 1, ops)
+        assert np.max(np.abs(back[:, [0, -1], :])) < 1e-12
+    bad2 = D.dfilt(u[1], +1, ops)                        # eq. (9): u2 even
+    # the wall value is of the size of the next row's, not zero
+    assert _rms(bad2[:, 0, :]) > 0.1 * _rms(bad2[:, 1, :])
+
+
+def test_eq9_extension_violates_eq11_for_the_gaussian_too():
+    from oracle import filter_ref as R
+    cfg = synth.config("tiny", nx=16, nz=12, ny=17)
+    ops = R.Operators.from_config(cfg)
+    y, u = synth.make_snapshot(cfg, 6)
+    u = u.astype(np.float64)
+    good = R.filt(u[1], -1, ops)
+    bad = R.filt(u[1], +1, ops)
+    assert np.max(np.abs(good[:, [0, -1], :])) < 1e-14
+    assert _rms(bad[:, 0, :]) > 0.1 * _rms(bad[:, 1, :])
