@@ -95,24 +95,53 @@ def cpu_baseline(cfg, u_host, budget_s):
             "sample": f"{reps} full {cfg.nx}x{cfg.ny}x{cfg.nz} snapshot(s), FP64 dense sums, {el:.1f} s"}, out
 
 
-def dfilter_pass_model(cfg):
+def dfilter_pass_model(cfg, nf=9, products=True):
     """Algorithmic bytes and matrix-core flops per grid point of each pass of
-    the differential-filter stress (nine filtered fields)."""
+    the differential filter: the stress (nine filtered fields, the first pass
+    forming them from u) or plain filtering / inverse filtering of nf
+    fields."""
     def fwd(n):   # folded forward transform: cosines 0..h and sines 1..hs over nodes 1..h
         h, hs = n // 2, (n - 1) // 2
         return 2.0 * h * (h + 1 + hs) / n
     def inv(n):   # folded inverse: P and Q sums for nodes 0..h over coefficients 1..h / 1..hs
         h, hs = n // 2, (n - 1) // 2
         return 2.0 * (h + 1) * (h + hs) / n
-    nf = 9
-    return {
-        "x_fwd": dict(bytes=48.0, flops=nf * fwd(cfg.nx), kernel="dfilter_xf"),   # reads u, writes 9 fields
-        "z_fwd": dict(bytes=72.0, flops=nf * fwd(cfg.nz), kernel="dfilter_zf"),
-        "y_solve": dict(bytes=72.0, flops=0.0, kernel="dfilter_y"),
-        "z_inv": dict(bytes=72.0, flops=nf * inv(cfg.nz), kernel="dfilter_zi"),
-        "x_inv": dict(bytes=72.0, flops=nf * inv(cfg.nx), kernel="dfilter_xi"),
-        "epilogue": dict(bytes=72.0, flops=0.0, kernel="dfilter_epi"),   # 9 fields in, ubar + tau out
+    fb = 8.0 * nf   # one read and one write of the fields
+    m = {
+        # stress: reads u (3 fields), writes 9
+        "x_fwd": dict(bytes=48.0 if products else fb, flops=nf * fwd(cfg.nx), kernel="dfilter_xf" if products else None),
+        "z_fwd": dict(bytes=fb, flops=nf * fwd(cfg.nz), kernel="dfilter_zf" if products else None),
+        "y_solve": dict(bytes=fb, flops=0.0, kernel="dfilter_y" if products else None),
+        "z_inv": dict(bytes=fb, flops=nf * inv(cfg.nz), kernel="dfilter_zi" if products else None),
+        "x_inv": dict(bytes=fb, flops=nf * inv(cfg.nx), kernel="dfilter_xi" if products else None),
     }
+    if products:
+        m["epilogue"] = dict(bytes=72.0, flops=0.0, kernel="dfilter_epi")   # 9 fields in, ubar + tau out
+    return m
+
+
+def dfilter_rooflines(cfg, model, prof, traffic_rec, counters):
+    """Per pass: the larger of the matrix-core and HBM fractions, from the
+    library's event timings."""
+    roofs = {}
+    for k, m in model.items():
+        ms, nl = prof[k]
+        t_k = ms / 1e3 / max(nl, 1)
+        gbs = m["bytes"] * cfg.points / t_k / 1e9
+        r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+        if m["flops"] > 0:
+            tfs = m["flops"] * cfg.points / t_k / 1e12
+            if tfs / FP32_MFMA_PEAK_TF >= r["frac"]:
+                r = {"bound": "mfma", "achieved": tfs, "peak": FP32_MFMA_PEAK_TF, "unit": "TFLOP/s",
+                     "frac": tfs / FP32_MFMA_PEAK_TF,
+                     "note": "folded real-transform multiply-adds on FP32 matrix cores; padding of the "
+                             "16x16 tiles and the K steps past n/2 are not counted"}
+        r["kernel"] = m["kernel"]
+        r["us_avg"] = 1e6 * t_k
+        tr = counters.current(traffic_rec, m["kernel"]) if m["kernel"] else None
+        r["traffic"] = tr["bytes"] if tr else None
+        roofs[k] = r
+    return roofs
 
 
 def dfilter_cpu_baseline(cfg, u_host, budget_s):
@@ -180,26 +209,36 @@ def main_differential(a):
 
     model = dfilter_pass_model(cfg)
     traffic_rec = counters.read_summary(os.path.join(ROOT, "profiles", f"hbm_traffic_{a.workload}_differential.md"))
-    roofs = {}
-    for k, m in model.items():
-        ms, nl = prof[k]
-        t_k = ms / 1e3 / max(nl, 1)
-        gbs = m["bytes"] * cfg.points / t_k / 1e9
-        r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
-        if m["flops"] > 0:
-            tfs = m["flops"] * cfg.points / t_k / 1e12
-            if tfs / FP32_MFMA_PEAK_TF >= r["frac"]:
-                r = {"bound": "mfma", "achieved": tfs, "peak": FP32_MFMA_PEAK_TF, "unit": "TFLOP/s",
-                     "frac": tfs / FP32_MFMA_PEAK_TF,
-                     "note": "folded real-transform multiply-adds on FP32 matrix cores; padding of the "
-                             "16x16 tiles and the K steps past n/2 are not counted"}
-        r["kernel"] = m["kernel"]
-        r["us_avg"] = 1e6 * t_k
-        tr = counters.current(traffic_rec, m["kernel"])
-        r["traffic"] = tr["bytes"] if tr else None
-        roofs[k] = r
+    roofs = dfilter_rooflines(cfg, model, prof, traffic_rec, counters)
     dom = max(model, key=lambda k: prof[k][0])
     passes = {k: {"us_avg": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in prof.items()}
+
+    # the inverse filter of the three filtered velocities, and the error
+    # measures of eqs. (13)-(15) against the unfiltered field
+    back = torch.empty_like(ubar[0])
+    eles.dfilter_profile_begin(f.h, a.steps)
+    for i in range(a.steps):
+        f.inverse(ubar[i % ns], [1, -1, 1], out=back)
+    prof_i = eles.dfilter_profile_end(f.h)
+    model_i = dfilter_pass_model(cfg, nf=3, products=False)
+    roofs_i = dfilter_rooflines(cfg, model_i, prof_i, None, counters)
+    dom_i = max(model_i, key=lambda k: prof_i[k][0])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f.errors(back, us[0], 1.0, 1.0)
+    e0.record()
+    for i in range(a.steps):
+        err = f.errors(back, us[(a.steps - 1) % ns], 1.0, 1.0)
+    e1.record()
+    torch.cuda.synchronize()
+    t_err = e0.elapsed_time(e1) / a.steps * 1e-3
+    err_bytes = 24.0 * cfg.points   # two velocity fields read once
+    inverse = {"us_per_call": sum(1e3 * ms / max(n, 1) for ms, n in prof_i.values()),
+               "passes": {k: round(1e3 * ms / max(n, 1), 2) for k, (ms, n) in prof_i.items() if n},
+               "roofline": roofs_i[dom_i], "fields": 3,
+               "round_trip_errors_eq13_15": [float(v) for v in err.cpu().numpy()]}
+    errors = {"us_per_call": 1e6 * t_err, "bytes": err_bytes,
+              "roofline": {"bound": "hbm", "achieved": err_bytes / t_err / 1e9, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": err_bytes / t_err / 1e9 / HBM_PEAK_GBS}}
 
     cpu = None
     parity = None
@@ -228,6 +267,8 @@ def main_differential(a):
         "cpu_baseline": cpu,
         "passes": passes,
         "max_rel_l2_vs_oracle": parity,
+        "inverse_filter": inverse,
+        "errors_eq13_15": errors,
     }
     print(json.dumps(line), flush=True)
 

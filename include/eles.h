@@ -234,12 +234,36 @@ int32_t dfilter_fields(eles_dfilter f, const float *in, int32_t nfields, const i
 int32_t dfilter_sgs_stress(eles_dfilter f, const float *u, float *ubar, float *tau, double *stats, void *ws,
                            size_t ws_bytes, hipStream_t stream);
 
-/* Per-pass GPU timing of later dfilter_sgs_stress / dfilter_fields calls on
- * this handle, with HIP events recorded on the call's stream around every
- * pass: 0 shift profile, 1 x forward transform (with the products), 2 z
- * forward transform, 3 y solves, 4 z inverse transform, 5 x inverse
- * transform, 6 stress epilogue and plane statistics (dfilter_fields times
- * passes 1 .. 5). dfilter_profile_begin creates events for up to max_calls
+/* The inverse filter, u = (1 - a^2 lap) ubar with the same discretisation
+ * (the operator the filter inverts; Sec. 4.2 compares unfiltered LES and
+ * DNS velocities through it). Arguments, parities, layouts, workspace size
+ * (dfilter_workspace_bytes) and errors as for dfilter_fields; odd outputs
+ * are exactly 0 on the wall planes. */
+int32_t dfilter_inverse(eles_dfilter f, const float *in, int32_t nfields, const int8_t *parity, float *out,
+                        void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Errors of an LES velocity against a DNS velocity on this grid, the forms
+ * of eqs. (13)-(15). les, dns: device [3][nx][ny][nz] (u1, u2, u3), each
+ * scaled by its friction velocity (utau_les, utau_dns > 0, finite). out:
+ * device FP64 [5]:
+ *   out[0] eq. (13): volume relative L2 error of u1, over the channel;
+ *   out[1] eq. (14): relative L2 error of the <u1>(y) profile;
+ *   out[2 + i] eq. (15): relative L2 error of the rms profile of u_{i+1};
+ * <.> is the average over x and z, rms = sqrt(<u^2> - <u>^2), and the
+ * profile integrals run from the lower wall to the centreline (nodes with
+ * y <= 0). Integrals in y use the bounded trapezoid rule on the nodes
+ * used; sums in FP64. Workspace: dfilter_errors_workspace_bytes. Errors:
+ * EINVAL, ENOSPACE, EHIP. */
+size_t dfilter_errors_workspace_bytes(eles_dfilter f);
+int32_t dfilter_errors(eles_dfilter f, const float *les, const float *dns, double utau_les, double utau_dns,
+                       double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Per-pass GPU timing of later dfilter_sgs_stress / dfilter_fields /
+ * dfilter_inverse calls on this handle, with HIP events recorded on the
+ * call's stream around every pass: 0 shift profile, 1 x forward transform (with the products), 2 z
+ * forward transform, 3 y solves (dfilter_inverse: the y operator), 4 z
+ * inverse transform, 5 x inverse transform, 6 stress epilogue and plane
+ * statistics (dfilter_fields and dfilter_inverse time passes 1 .. 5). dfilter_profile_begin creates events for up to max_calls
  * calls (host-side HIP events; no device memory); dfilter_profile_end waits
  * for the device and returns, per pass, the summed milliseconds and the
  * number of timed launches, then releases the events. Errors: EINVAL,

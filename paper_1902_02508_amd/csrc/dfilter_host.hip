@@ -49,7 +49,7 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
   return pa < pb + nb && pb < pa + na;
 }
 
-enum { D_Y, D_D64, D_P64, D_S64, D_FX, D_IX, D_FZ, D_IZ, D_LO, D_CP, D_INV, D_PROF, D_END };
+enum { D_Y, D_D64, D_P64, D_S64, D_FX, D_IX, D_FZ, D_IZ, D_LO, D_OP, D_CP, D_INV, D_PROF, D_END };
 
 struct DPlan {
   eles::DAxis ax, az;
@@ -84,6 +84,7 @@ int32_t plan_d(const eles_dfilter_desc *d, DPlan *p) {
                             eles::dtab_fwd_floats(p->az) * 4,
                             eles::dtab_inv_floats(p->az) * 4,
                             2 * ny * 4,
+                            6 * ny * 4,
                             nfac * 4,
                             nfac * 4,
                             3 * ny * 4};
@@ -140,6 +141,7 @@ int32_t dfilter_setup(const eles_dfilter_desc *desc, void *state, size_t state_b
   v.fz = (float *)(s + p.off[D_FZ]);
   v.iz = (float *)(s + p.off[D_IZ]);
   v.lo32 = (float *)(s + p.off[D_LO]);
+  v.op32 = (float *)(s + p.off[D_OP]);
   v.cp = (float *)(s + p.off[D_CP]);
   v.inv = (float *)(s + p.off[D_INV]);
   v.prof = (float *)(s + p.off[D_PROF]);
@@ -242,6 +244,46 @@ int32_t dfilter_profile_end(eles_dfilter f, double *ms, int32_t *launches) {
   }
   release_events(f);
   return st;
+}
+
+int32_t dfilter_inverse(eles_dfilter f, const float *in, int32_t nfields, const int8_t *parity, float *out,
+                        void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!f || !in || !out || !parity || !ws || nfields < 1 || nfields > 32) return ELES_EINVAL;
+  if (!aligned16(in) || !aligned16(out) || !aligned16(ws)) return ELES_EINVAL;
+  unsigned pmask = 0;
+  for (int k = 0; k < nfields; ++k) {
+    if (parity[k] != 1 && parity[k] != -1) return ELES_EINVAL;
+    if (parity[k] < 0) pmask |= 1u << k;
+  }
+  const size_t bytes = (size_t)nfields * f->npts * sizeof(float);
+  if (overlap(in, bytes, out, bytes)) return ELES_EINVAL;
+  if (ws_bytes < dfilter_workspace_bytes(f, nfields)) return ELES_ENOSPACE;
+  if (overlap(ws, ws_bytes, in, bytes) || overlap(ws, ws_bytes, out, bytes)) return ELES_EINVAL;
+  float *w0 = (float *)ws;
+  float *w1 = (float *)((char *)ws + up256(bytes));
+  return eles::launch_dinverse(f->v, in, nfields, pmask, w0, w1, out, stream, call_events(f, false)) == hipSuccess
+             ? ELES_OK
+             : ELES_EHIP;
+}
+
+size_t dfilter_errors_workspace_bytes(eles_dfilter f) {
+  if (!f) return 0;
+  return up256((size_t)eles::derr_parts(f->v) * sizeof(double));
+}
+
+int32_t dfilter_errors(eles_dfilter f, const float *les, const float *dns, double utau_les, double utau_dns,
+                       double *out, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!f || !les || !dns || !out || !ws) return ELES_EINVAL;
+  if (!aligned16(les) || !aligned16(dns) || !aligned16(ws) || ((uintptr_t)out & 7u)) return ELES_EINVAL;
+  if (!(std::isfinite(utau_les) && utau_les > 0) || !(std::isfinite(utau_dns) && utau_dns > 0)) return ELES_EINVAL;
+  if (ws_bytes < dfilter_errors_workspace_bytes(f)) return ELES_ENOSPACE;
+  const size_t n = 3 * f->npts * sizeof(float);
+  if (overlap(ws, ws_bytes, les, n) || overlap(ws, ws_bytes, dns, n) || overlap(ws, ws_bytes, out, 5 * 8) ||
+      overlap(out, 5 * 8, les, n) || overlap(out, 5 * 8, dns, n))
+    return ELES_EINVAL;
+  return eles::launch_derrors(f->v, les, dns, utau_les, utau_dns, (double *)ws, out, stream) == hipSuccess
+             ? ELES_OK
+             : ELES_EHIP;
 }
 
 void dfilter_destroy(eles_dfilter f) {

@@ -248,6 +248,7 @@ struct DView {
   double *scratch64;            // [3][ny]
   float *fx, *ix, *fz, *iz;     // forward and inverse tables of x and z
   float *lo32;                  // [2][ny] system sub-diagonal -a^2 sub
+  float *op32;                  // [2][3][ny] -a^2 (sub, main, super) of the y difference
   float *cp, *inv;              // [2][hx + 1][ny][hz + 1] elimination factors
   float *prof;                  // [3][ny] m, M = F(m), F(m^2) - M^2
 };
@@ -258,6 +259,14 @@ hipError_t launch_dfilter(const DView &v, const float *in, int nf, unsigned pmas
                           hipStream_t s, const hipEvent_t *ev);
 hipError_t launch_dsgs(const DView &v, const float *u, float *w0, float *w1, float *ubar, float *tau,
                        double *part, double *stats, hipStream_t s, const hipEvent_t *ev);
+// the inverse filter u = (1 - a^2 lap) ubar with the same discretisation
+hipError_t launch_dinverse(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1,
+                           float *out, hipStream_t s, const hipEvent_t *ev);
+// eq. (13)-(15) errors of les against dns ([3][nx][ny][nz] each) into
+// out[5] (FP64, device); part: derr_parts doubles
+hipError_t launch_derrors(const DView &v, const float *les, const float *dns, double utau_les, double utau_dns,
+                          double *part, double *out, hipStream_t s);
+long derr_parts(const DView &v);
 long dsgs_parts(const DView &v);   // doubles of the statistics scratch of launch_dsgs
 
 }  // namespace eles

@@ -217,7 +217,10 @@ __global__ void k_dfactor(DView v) {
     cprev = cj;
   }
   if (col == 0)
-    for (int j = 0; j < ny; ++j) v.lo32[(size_t)p * ny + j] = (float)(-a2 * d[j]);
+    for (int j = 0; j < ny; ++j) {
+      v.lo32[(size_t)p * ny + j] = (float)(-a2 * d[j]);
+      for (int r = 0; r < 3; ++r) v.op32[((size_t)p * 3 + r) * ny + j] = (float)(-a2 * d[r * ny + j]);
+    }
 }
 
 // ---------------------------------------------------------------- per call
@@ -922,10 +925,164 @@ __global__ void __launch_bounds__(256) k_dsolve(DView v, const float *__restrict
   }
 }
 
+constexpr int kDXC = 16;   // x planes per block of the plane-sum kernels
+
+// The operator itself in the coefficient space, out of place: for every
+// (field, qx, qz) column, out_j = (1 + a^2 (kx^2 + kz^2)) x_j - a^2 (D x)_j
+// with the reflected three-point difference D of the field's parity; odd
+// fields are zero on the wall rows. FP64 wavenumber term, FP32 products.
+__global__ void __launch_bounds__(256) k_dapply(DView v, const float *__restrict__ in, float *__restrict__ out,
+                                                int nf, unsigned pmask) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nx = v.nx, ny = v.ny, nz = v.nz;
+  const long ncolf = (long)nx * nz;
+  if (t >= nf * ncolf) return;
+  const int f = (int)(t / ncolf);
+  const long col = t - f * ncolf;
+  const int qx = (int)(col / nz), qz = (int)(col - (long)qx * nz);
+  const int p = (pmask >> f) & 1;
+  const double kx = 2.0 * M_PI * widx(qx, nx) / v.lx, kz = 2.0 * M_PI * widx(qz, nz) / v.lz;
+  const float c = (float)(1.0 + v.a * v.a * (kx * kx + kz * kz));
+  const float *__restrict__ lo = v.op32 + (size_t)p * 3 * ny;
+  const float *__restrict__ mi = lo + ny;
+  const float *__restrict__ hi = lo + 2 * ny;
+  const size_t base = (size_t)f * nx * ny * nz + (size_t)qx * ny * nz + qz;
+  const float *__restrict__ x = in + base;
+  float *__restrict__ y = out + base;
+  const int j0 = p, j1 = ny - 1 - p;
+  // sliding window x_{j-1}, x_j, x_{j+1}; neighbours outside j0 .. j1 carry
+  // zero coefficients
+  float xm = 0.0f, x0 = x[(size_t)j0 * nz];
+  for (int jb = j0; jb <= j1; jb += kCH) {
+    float nxt[kCH];
+#pragma unroll
+    for (int c8 = 0; c8 < kCH; ++c8) nxt[c8] = x[(size_t)min(jb + c8 + 1, j1) * nz];
+#pragma unroll
+    for (int c8 = 0; c8 < kCH; ++c8) {
+      const int j = jb + c8;
+      if (j > j1) break;
+      const float xp = j < j1 ? nxt[c8] : 0.0f;
+      y[(size_t)j * nz] = (c + mi[j]) * x0 + (lo[j] * xm + hi[j] * xp);
+      xm = x0;
+      x0 = xp;
+    }
+  }
+  if (p) {
+    y[0] = 0.0f;
+    y[(size_t)(ny - 1) * nz] = 0.0f;
+  }
+}
+
+// Errors of eqs. (13)-(15), partial sums. Block (xc, y) over kDXC x planes:
+// q = 0: sum (a1/ut_a - b1/ut_d)^2; 1: sum (b1/ut_d)^2; 2 + 4 i + (0 .. 3):
+// sums of a_i, a_i^2, b_i, b_i^2 (FP64), part[(q ny + y) nxc + xc].
+constexpr int kEQ = 14;
+__global__ void __launch_bounds__(256) k_eparts(DView v, const float *__restrict__ la, const float *__restrict__ db,
+                                                double inv_ua, double inv_ud, double *__restrict__ part) {
+  __shared__ double red[4][kEQ];
+  const int xc = blockIdx.x, y = blockIdx.y, nxc = gridDim.x;
+  const int nz = v.nz, ny = v.ny;
+  const int x0 = xc * kDXC, x1 = min(v.nx, x0 + kDXC);
+  const size_t n = (size_t)v.nx * ny * nz;
+  double s[kEQ];
+#pragma unroll
+  for (int q = 0; q < kEQ; ++q) s[q] = 0.0;
+  const int cnt = (x1 - x0) * nz;
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int xo = e / nz, z = e - xo * nz;
+    const size_t t = ((size_t)(x0 + xo) * ny + y) * nz + z;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double a = la[i * n + t], b = db[i * n + t];
+      if (i == 0) {
+        const double d = a * inv_ua - b * inv_ud;
+        s[0] += d * d;
+        s[1] += (b * inv_ud) * (b * inv_ud);
+      }
+      s[2 + 4 * i] += a;
+      s[3 + 4 * i] += a * a;
+      s[4 + 4 * i] += b;
+      s[5 + 4 * i] += b * b;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kEQ; ++q)
+    for (int off = 32; off > 0; off >>= 1) s[q] += __shfl_xor(s[q], off);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < kEQ; ++q) red[threadIdx.x >> 6][q] = s[q];
+  __syncthreads();
+  if (threadIdx.x < kEQ) {
+    const int q = threadIdx.x;
+    part[((size_t)q * ny + y) * nxc + xc] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+  }
+}
+
+// The partial sums over x chunks in order, the profiles, and the trapezoid
+// integrals over y (bounded trapezoid on the nodes used); threads take y
+// nodes, a block reduction adds their terms: out[0] eq. (13) over the
+// channel; out[1] eq. (14) and out[2 .. 4] eq. (15) for u1, u2, u3 over the
+// lower half, y <= 0 (wall to centreline).
+constexpr int kET = 10;   // integral terms
+__global__ void __launch_bounds__(256) k_efinal(DView v, const double *__restrict__ part, int nxc, double inv_ua,
+                                                double inv_ud, double *__restrict__ out) {
+  __shared__ double red[4][kET];
+  const int ny = v.ny;
+  const double *y = v.y64;
+  const double cnt = (double)v.nx * v.nz;
+  double acc[kET];   // n13, d13, n14, d14, n15[3], d15[3]
+#pragma unroll
+  for (int q = 0; q < kET; ++q) acc[q] = 0.0;
+  for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+    double sm[kEQ];
+#pragma unroll
+    for (int q = 0; q < kEQ; ++q) {
+      double t = 0.0;
+      for (int c = 0; c < nxc; ++c) t += part[((size_t)q * ny + j) * nxc + c];
+      sm[q] = t;
+    }
+    const double lo = j > 0 ? y[j] - y[j - 1] : 0.0;
+    const double hi = j < ny - 1 ? y[j + 1] - y[j] : 0.0;
+    const double w = 0.5 * (lo + hi);
+    acc[0] += w * sm[0];
+    acc[1] += w * sm[1];
+    if (y[j] <= 0.0) {
+      // half-channel trapezoid: the upper neighbour only if it is in the half
+      const double wh = 0.5 * (lo + (j < ny - 1 && y[j + 1] <= 0.0 ? hi : 0.0));
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double ma = sm[2 + 4 * i] / cnt, qa = sm[3 + 4 * i] / cnt;
+        const double mb = sm[4 + 4 * i] / cnt, qb = sm[5 + 4 * i] / cnt;
+        const double ra = sqrt(fmax(qa - ma * ma, 0.0)) * inv_ua, rb = sqrt(fmax(qb - mb * mb, 0.0)) * inv_ud;
+        if (i == 0) {
+          const double d = ma * inv_ua - mb * inv_ud;
+          acc[2] += wh * d * d;
+          acc[3] += wh * (mb * inv_ud) * (mb * inv_ud);
+        }
+        acc[4 + i] += wh * (ra - rb) * (ra - rb);
+        acc[7 + i] += wh * rb * rb;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kET; ++q)
+    for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < kET; ++q) red[threadIdx.x >> 6][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[kET];
+    for (int q = 0; q < kET; ++q) t[q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+    out[0] = sqrt(t[0] / t[1]);
+    out[1] = sqrt(t[2] / t[3]);
+    for (int i = 0; i < 3; ++i) out[2 + i] = sqrt(t[4 + i] / t[7 + i]);
+  }
+}
+
 // ubar and tau from the nine filtered fields g. Block (xc, y): the points
 // of kDXC x planes at wall-normal index y; with part, also the FP64 sums of
 // the nine outputs over those points, part[(q ny + y) nxc + xc].
-constexpr int kDXC = 16;
 __global__ void __launch_bounds__(256) k_depi(DView v, const float *__restrict__ g, float *__restrict__ ubar,
                                               float *__restrict__ tau, double *__restrict__ part) {
   __shared__ double red[4][kDFields];
@@ -1042,7 +1199,7 @@ void mark(const hipEvent_t *ev, int idx, hipStream_t s) {
   if (ev) (void)hipEventRecord(ev[idx], s);
 }
 
-template <bool SGS>
+template <bool SGS, bool APPLY = false>
 hipError_t run_filter(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1, float *out,
                       hipStream_t s, const hipEvent_t *ev) {
   const int nb = SGS ? kDFields : nf;
@@ -1054,7 +1211,10 @@ hipError_t run_filter(const DView &v, const float *in, int nf, unsigned pmask, f
   mark(ev, 2 * kDPassZf + 1, s);
   const int ns = SGS ? 6 : nf;
   mark(ev, 2 * kDPassY, s);
-  k_dsolve<SGS><<<grid_of((long)ns * v.nx * v.nz, 256), 256, 0, s>>>(v, w0, w1, nf, pmask);
+  if (APPLY)
+    k_dapply<<<grid_of((long)nf * v.nx * v.nz, 256), 256, 0, s>>>(v, w0, w1, nf, pmask);
+  else
+    k_dsolve<SGS><<<grid_of((long)ns * v.nx * v.nz, 256), 256, 0, s>>>(v, w0, w1, nf, pmask);
   mark(ev, 2 * kDPassY + 1, s);
   mark(ev, 2 * kDPassZi, s);
   inv<true>(targs(v, false, v.iz, w1, w0, nb), s);
@@ -1084,6 +1244,21 @@ hipError_t launch_dsetup(const DView &v, hipStream_t s) {
 hipError_t launch_dfilter(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1, float *out,
                           hipStream_t s, const hipEvent_t *ev) {
   return run_filter<false>(v, in, nf, pmask, w0, w1, out, s, ev);
+}
+
+hipError_t launch_dinverse(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1,
+                           float *out, hipStream_t s, const hipEvent_t *ev) {
+  return run_filter<false, true>(v, in, nf, pmask, w0, w1, out, s, ev);
+}
+
+long derr_parts(const DView &v) { return (long)kEQ * v.ny * ((v.nx + kDXC - 1) / kDXC); }
+
+hipError_t launch_derrors(const DView &v, const float *les, const float *dns, double utau_les, double utau_dns,
+                          double *part, double *out, hipStream_t s) {
+  const int nxc = (v.nx + kDXC - 1) / kDXC;
+  k_eparts<<<dim3(nxc, v.ny), 256, 0, s>>>(v, les, dns, 1.0 / utau_les, 1.0 / utau_dns, part);
+  k_efinal<<<1, 256, 0, s>>>(v, part, nxc, 1.0 / utau_les, 1.0 / utau_dns, out);
+  return hipGetLastError();
 }
 
 // u [3][nx][ny][nz] -> ubar [3], tau [6]; w0, w1: workspaces of nine

@@ -83,6 +83,9 @@ _SIG = {
     "dfilter_fields": (_I, [_P, _P, _I, _P, _P, _P, _S, _P]),
     "dfilter_sgs_stress": (_I, [_P, _P, _P, _P, _P, _P, _S, _P]),
     "dfilter_destroy": (None, [_P]),
+    "dfilter_inverse": (_I, [_P, _P, _I, _P, _P, _P, _S, _P]),
+    "dfilter_errors_workspace_bytes": (_S, [_P]),
+    "dfilter_errors": (_I, [_P, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P, _S, _P]),
     "dfilter_profile_begin": (_I, [_P, _I]),
     "dfilter_profile_end": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)]),
     "closure_state_bytes": (_S, []),
@@ -278,6 +281,32 @@ class Filter:
         ws = self._workspace(nb)
         filter_fields(self.h, _ptr(fields), nf, ctypes.cast(par, ctypes.c_void_p), _ptr(out),
                       _ptr(ws), ws.numel(), _stream())
+        return out
+
+    def inverse(self, fields: torch.Tensor, parity: Sequence[int], out: Optional[torch.Tensor] = None):
+        """u = (1 - a^2 lap) ubar, field by field."""
+        nf = fields.shape[0]
+        self._field_check(fields, nf)
+        if out is None:
+            out = torch.empty_like(fields)
+        self._field_check(out, nf)
+        if len(parity) != nf or any(int(p) not in (1, -1) for p in parity):
+            raise ValueError("one parity (+1 even, -1 odd) per field")
+        par = (ctypes.c_int8 * nf)(*[int(p) for p in parity])
+        ws = self._workspace(dfilter_workspace_bytes(self.h, nf))
+        dfilter_inverse(self.h, _ptr(fields), nf, ctypes.cast(par, ctypes.c_void_p), _ptr(out),
+                        _ptr(ws), ws.numel(), _stream())
+        return out
+
+    def errors(self, les: torch.Tensor, dns: torch.Tensor, utau_les: float, utau_dns: float):
+        """Device FP64 [5]: eq. (13) volume error of u1, eq. (14) <u1> profile
+        error, eq. (15) rms profile errors of u1, u2, u3."""
+        self._field_check(les, 3)
+        self._field_check(dns, 3)
+        out = torch.empty(5, dtype=torch.float64, device=self.device)
+        ws = self._workspace(dfilter_errors_workspace_bytes(self.h))
+        dfilter_errors(self.h, _ptr(les), _ptr(dns), utau_les, utau_dns, _ptr(out), _ptr(ws), ws.numel(),
+                       _stream())
         return out
 
     def sgs_stress(self, u: torch.Tensor, ubar=None, tau=None, stats=True):
@@ -523,6 +552,19 @@ def dfilter_destroy(h):
     lib.dfilter_destroy(h)
 
 
+def dfilter_inverse(h, in_ptr, nfields, parity_ptr, out_ptr, ws_ptr, ws_bytes, stream):
+    _check(lib.dfilter_inverse(h, in_ptr, nfields, parity_ptr, out_ptr, ws_ptr, ws_bytes, stream), "dfilter_inverse")
+
+
+def dfilter_errors_workspace_bytes(h) -> int:
+    return lib.dfilter_errors_workspace_bytes(h)
+
+
+def dfilter_errors(h, les_ptr, dns_ptr, utau_les, utau_dns, out_ptr, ws_ptr, ws_bytes, stream):
+    _check(lib.dfilter_errors(h, les_ptr, dns_ptr, float(utau_les), float(utau_dns), out_ptr, ws_ptr, ws_bytes,
+                              stream), "dfilter_errors")
+
+
 DNPASS = 7
 DPASS_NAMES = ("shift", "x_fwd", "z_fwd", "y_solve", "z_inv", "x_inv", "epilogue")
 
@@ -596,6 +638,32 @@ class DFilter:
         ws = self._workspace(dfilter_workspace_bytes(self.h, nf))
         dfilter_fields(self.h, _ptr(fields), nf, ctypes.cast(par, ctypes.c_void_p), _ptr(out),
                        _ptr(ws), ws.numel(), _stream())
+        return out
+
+    def inverse(self, fields: torch.Tensor, parity: Sequence[int], out: Optional[torch.Tensor] = None):
+        """u = (1 - a^2 lap) ubar, field by field."""
+        nf = fields.shape[0]
+        self._field_check(fields, nf)
+        if out is None:
+            out = torch.empty_like(fields)
+        self._field_check(out, nf)
+        if len(parity) != nf or any(int(p) not in (1, -1) for p in parity):
+            raise ValueError("one parity (+1 even, -1 odd) per field")
+        par = (ctypes.c_int8 * nf)(*[int(p) for p in parity])
+        ws = self._workspace(dfilter_workspace_bytes(self.h, nf))
+        dfilter_inverse(self.h, _ptr(fields), nf, ctypes.cast(par, ctypes.c_void_p), _ptr(out),
+                        _ptr(ws), ws.numel(), _stream())
+        return out
+
+    def errors(self, les: torch.Tensor, dns: torch.Tensor, utau_les: float, utau_dns: float):
+        """Device FP64 [5]: eq. (13) volume error of u1, eq. (14) <u1> profile
+        error, eq. (15) rms profile errors of u1, u2, u3."""
+        self._field_check(les, 3)
+        self._field_check(dns, 3)
+        out = torch.empty(5, dtype=torch.float64, device=self.device)
+        ws = self._workspace(dfilter_errors_workspace_bytes(self.h))
+        dfilter_errors(self.h, _ptr(les), _ptr(dns), utau_les, utau_dns, _ptr(out), _ptr(ws), ws.numel(),
+                       _stream())
         return out
 
     def sgs_stress(self, u: torch.Tensor, ubar=None, tau=None, stats=True):

@@ -116,3 +116,76 @@ def test_dfilter_sgs_stress_matches_oracle(E, label, base, over, seed):
     # FP64 plane statistics equal the plane means of the outputs
     mine = np.concatenate([R.plane_mean(ub), R.plane_mean(tau)])
     assert np.max(np.abs(st - mine)) < 1e-12 * (1 + np.abs(mine).max())
+
+
+# ---- the inverse filter and the error measures (eqs. (11), (13)-(15))
+
+@pytest.mark.parametrize("label,base,over", GRIDS)
+def test_dfilter_inverse_matches_oracle(E, label, base, over):
+    """u = (1 - a^2 lap) ubar against the oracle's operator. Its eigenvalues
+    are >= 1, so the FP32 transform roundings stay a few 2^-24 sqrt(n) of
+    the output: 2e-6 relative L2, as for the filter."""
+    cfg = synth.config(base, **over)
+    y = synth.ygrid(cfg.ny, cfg.ykind, cfg.stretch)
+    rng = np.random.default_rng(31)
+    par = [1, -1, 1]
+    v = rng.standard_normal((len(par), cfg.nx, cfg.ny, cfg.nz)).astype(np.float32) - 0.3
+    v[1][:, [0, -1], :] = 0.0
+    f = E.DFilter.from_config(cfg)
+    out = _host(f.inverse(_dev(v), par))
+    ops = D.DOperators.from_config(cfg)
+    for k, p in enumerate(par):
+        ref = D.laplacian_apply(v[k].astype(np.float64), p, ops)
+        err = R.rel_l2(out[k], ref, y)
+        print(label, "inverse", k, f"{err:.2e}", flush=True)
+        assert err < 2e-6, (label, k, err)
+        if p < 0:
+            assert np.all(out[k][:, [0, -1], :] == 0.0)
+
+
+@pytest.mark.parametrize("label,base,over", GRIDS[:4] + [("dns192", "dns192", dict())])
+def test_dfilter_round_trip_and_eq11(E, label, base, over):
+    """inverse(filter(u)) = u on the GPU; with the eq. (7) parities the
+    filtered u2 vanishes on the walls and the inverse returns the no-slip
+    wall values (eq. (11)); with the eq. (9) parities ubar_2 does not."""
+    cfg = synth.config(base, **over)
+    y, u = synth.make_snapshot(cfg, 7)
+    f = E.DFilter.from_config(cfg)
+    du = _dev(u)
+    ub = f.filter_fields(du, [1, -1, 1])
+    back = _host(f.inverse(ub, [1, -1, 1]))
+    # the inverse multiplies the FP32 rounding of ubar by up to the operator's
+    # infinity norm 1 + a^2 (kx_max^2 + kz_max^2) + a^2 max_j sum |D_jk|
+    # (large next to clustered wall nodes)
+    ops = D.DOperators.from_config(cfg)
+    lo, di, hi = D.second_difference(ops.y, 1)
+    norm = 1.0 + ops.a ** 2 * (np.max(ops.k2) + np.max(np.abs(lo) + np.abs(di) + np.abs(hi)))
+    for k in range(3):
+        err = R.rel_l2(back[k], u[k], y)
+        tol_k = max(2e-5, 8 * 2.0 ** -24 * norm)
+        print(label, "round trip", k, f"{err:.2e} (tol {tol_k:.1e}, operator norm {norm:.0f})", flush=True)
+        assert err < tol_k, (label, k, err)
+    assert np.all(_host(ub)[1][:, [0, -1], :] == 0.0)
+    tol = 32 * 2.0 ** -24 * norm * float(np.max(np.abs(_host(ub))))
+    wall = float(np.max(np.abs(back[:, :, [0, -1], :])))
+    print(label, f"wall {wall:.2e} (tol {tol:.1e})", flush=True)
+    assert wall < tol
+    bad = _host(f.filter_fields(du[1:2].clone(), [1]))[0]   # own allocation: 16-byte aligned
+    rms = lambda a: float(np.sqrt(np.mean(a ** 2)))
+    assert rms(bad[:, 0, :]) > 0.1 * rms(bad[:, 1, :])
+
+
+@pytest.mark.parametrize("label,base,over", [GRIDS[0], GRIDS[2], ("dns192", "dns192", dict())])
+def test_dfilter_errors_match_oracle(E, label, base, over):
+    from oracle import metrics_ref as M
+    cfg = synth.config(base, **over)
+    y, u = synth.make_snapshot(cfg, 8)
+    _, w = synth.make_snapshot(cfg, 9)
+    les = (u + 0.05 * w).astype(np.float32)
+    f = E.DFilter.from_config(cfg)
+    got = _host(f.errors(_dev(les), _dev(u), 1.07, 1.0))
+    ref = M.errors(les.astype(np.float64), u.astype(np.float64), 1.07, 1.0, y)
+    print(label, "errors", got, ref, flush=True)
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-10
+    same = _host(f.errors(_dev(u), _dev(u), 1.0, 1.0))
+    assert np.all(same == 0.0)

@@ -52,6 +52,8 @@ def test_mean_profile_offset_closed_form():
     U = 1.0 - y ** 2
     dns = np.zeros((3, nx, ny, nz))
     dns[0] = U[None, :, None]
+    x = np.arange(nx) / nx
+    dns[1] = dns[2] = np.sin(2 * math.pi * x)[:, None, None]   # nonzero intensities
     les = dns.copy()
     c = 0.05
     les[0] += c
