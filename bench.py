@@ -164,6 +164,37 @@ def dfilter_cpu_baseline(cfg, u_host, budget_s):
             "sample": f"{reps} full {cfg.nx}x{cfg.ny}x{cfg.nz} snapshot(s), FP64 FFT + Thomas, {el:.1f} s"}, out
 
 
+def les_grid_measure(cfg, eles, torch, ubar, tau, steps):
+    """The stress on the LES2 and LES4 grids (coarser by 2 and 4, linear
+    interpolation as the discretization operator) from this run's DNS-grid
+    outputs, timed with events on the library's stream, and the commutation
+    error of the interpolation with the y derivative for ubar_1 and tau_12.
+    Bytes: nine fields read at the DNS nodes the interpolation touches (the
+    eight corners of every LES node, at most every DNS node) and nine LES
+    fields written."""
+    out = {}
+    ns = len(ubar)
+    for r in (2, 4):
+        g = eles.LesGrid.coarsened(cfg, r)
+        ul, T = g.stress(ubar[0], tau[0])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(steps):
+            g.stress(ubar[i % ns], tau[i % ns], ul, T)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / steps * 1e-3
+        nles = g.les_shape[0] * g.les_shape[1] * g.les_shape[2]
+        byt = 36.0 * (min(cfg.points, 8 * nles) + nles)
+        c_u = float(g.commutation(ubar[0][0])[0])
+        c_t = float(g.commutation(tau[0][1])[0])
+        out[f"les{r}"] = {"shape": list(g.les_shape), "us": 1e6 * t, "bytes": byt,
+                          "hbm_frac": byt / t / 1e9 / HBM_PEAK_GBS,
+                          "commutation_error_ubar1": c_u, "commutation_error_tau12": c_t}
+    return out
+
+
 def main_differential(a):
     import numpy as np
     import torch
@@ -364,6 +395,8 @@ def main():
     dom = max(("xz", "y"), key=lambda k: prof[k][0])
     roof = roofs[dom]
 
+    les = les_grid_measure(cfg, eles, torch, ubar, tau, a.steps)
+
     cpu = None
     parity = None
     if a.cpu_seconds > 0:
@@ -392,6 +425,7 @@ def main():
         "cpu_baseline": cpu,
         "passes": passes,
         "max_rel_l2_vs_oracle": parity,
+        "les_grid": les,
     }
     print(json.dumps(line), flush=True)
 

@@ -276,6 +276,55 @@ int32_t dfilter_profile_end(eles_dfilter f, double *ms /* [ELES_DNPASS] */,
 void dfilter_destroy(eles_dfilter f);
 
 /* ======================================================================
+ * The stress on an LES grid (Sec. 2, the discrete filtered equations):
+ * T_ij = I(F(u_i u_j)) - I(F(u_i)) I(F(u_j)), with I the discretization
+ * operator, second-order linear interpolation from the DNS grid to the LES
+ * grid (Sec. 4; the LES2 / LES4 grids are coarser by 2 and 4), and the
+ * commutation error of I with second-order differentiation, which the
+ * paper notes for stretched meshes (Sec. 4).
+ *
+ * Interpolation: separable, periodic in x and z (LES node k at k L/n_les,
+ * DNS node i at i L/n), in y between the bracketing DNS nodes. It works
+ * from the DNS-grid outputs of either filter: with F(u_i u_j) = tau_ij +
+ * ubar_i ubar_j and weights summing to one, T_ij is I(tau_ij) plus the
+ * weighted covariance of the eight corner values of ubar.
+ * ====================================================================== */
+typedef struct {
+  int32_t nx, ny, nz;          /* DNS grid; ny >= 3                              */
+  const double *y;             /* host, ny nodes, increasing, y[0] = -1, y[ny-1] = 1 */
+  int32_t nx_les, ny_les, nz_les; /* LES grid; ny_les >= 3                       */
+  const double *y_les;         /* host, ny_les nodes, increasing, within [-1, 1] */
+} eles_les_desc;
+
+typedef struct eles_les_s *eles_les;
+
+/* Device bytes of the state (weights, indices, derivative stencils); 0 if
+ * the descriptor is invalid. */
+size_t les_state_bytes(const eles_les_desc *desc);
+
+/* Build the interpolation and stencils (FP64 on the host; weights stored in
+ * FP32, stencils in FP64) and copy them into state; waits for the stream.
+ * Errors: EINVAL, ENOSPACE, EHIP. */
+int32_t les_setup(const eles_les_desc *desc, void *state, size_t state_bytes, hipStream_t stream, eles_les *out);
+
+/* ubar_les [3] = I(ubar_i) and T [6] (order 11, 12, 13, 22, 23, 33) on the
+ * LES grid [nx_les][ny_les][nz_les], from ubar [3] and tau [6] on the DNS
+ * grid (the outputs of sgs_stress or dfilter_sgs_stress). FP32. Outputs
+ * must not overlap the inputs or each other. Errors: EINVAL, EHIP. */
+int32_t les_stress(eles_les h, const float *ubar, const float *tau, float *ubar_les, float *T, hipStream_t stream);
+
+/* Commutation error of one DNS field g [nx][ny][nz] (FP64, device out[1]):
+ * ||d_y^LES(I g) - I(d_y^DNS g)|| / ||I(d_y^DNS g)|| over the LES volume
+ * (uniform in x and z, trapezoid in y), d_y the three-point second-order
+ * first derivative on each mesh (one-sided three-point at the walls).
+ * Workspace: les_commutation_workspace_bytes. Errors: EINVAL, ENOSPACE,
+ * EHIP. */
+size_t les_commutation_workspace_bytes(eles_les h);
+int32_t les_commutation(eles_les h, const float *g, double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+void les_destroy(eles_les h);
+
+/* ======================================================================
  * Learned closure of the exact stress.
  *
  * The paper proposes using the exact stress computed from DNS data to

@@ -269,4 +269,21 @@ hipError_t launch_derrors(const DView &v, const float *les, const float *dns, do
 long derr_parts(const DView &v);
 long dsgs_parts(const DView &v);   // doubles of the statistics scratch of launch_dsgs
 
+// LES-grid stress and commutation error (k_les.hip).
+struct LesView {
+  int nx, ny, nz;               // DNS grid
+  int nxl, nyl, nzl;            // LES grid
+  const int *ix, *iy, *iz;      // lower DNS node of every LES node, per direction
+  const float *wx, *wy, *wz;    // weight of the upper DNS node
+  const int *db;                // DNS y derivative: first node of the stencil of node j
+  const double *dc;             //   its three coefficients [ny][3]
+  const int *lb;                // LES y derivative, the same
+  const double *lc;             //   [nyl][3]
+  const double *lw;             // LES y trapezoid weights [nyl]
+};
+hipError_t launch_les_stress(const LesView &v, const float *ubar, const float *tau, float *ul, float *T,
+                             hipStream_t s);
+long les_comm_parts(const LesView &v);   // doubles of the commutation-error scratch
+hipError_t launch_les_commutation(const LesView &v, const float *g, double *part, double *out, hipStream_t s);
+
 }  // namespace eles

@@ -42,6 +42,15 @@ class DFilterDesc(ctypes.Structure):
     ]
 
 
+class LesDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("y", ctypes.POINTER(ctypes.c_double)),
+        ("nx_les", ctypes.c_int32), ("ny_les", ctypes.c_int32), ("nz_les", ctypes.c_int32),
+        ("y_les", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
 class StateLayout(ctypes.Structure):
     _fields_ = [
         ("mx", ctypes.c_int32), ("mz", ctypes.c_int32),
@@ -86,6 +95,12 @@ _SIG = {
     "dfilter_inverse": (_I, [_P, _P, _I, _P, _P, _P, _S, _P]),
     "dfilter_errors_workspace_bytes": (_S, [_P]),
     "dfilter_errors": (_I, [_P, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P, _S, _P]),
+    "les_state_bytes": (_S, [ctypes.POINTER(LesDesc)]),
+    "les_setup": (_I, [ctypes.POINTER(LesDesc), _P, _S, _P, ctypes.POINTER(_P)]),
+    "les_stress": (_I, [_P, _P, _P, _P, _P, _P]),
+    "les_commutation_workspace_bytes": (_S, [_P]),
+    "les_commutation": (_I, [_P, _P, _P, _P, _S, _P]),
+    "les_destroy": (None, [_P]),
     "dfilter_profile_begin": (_I, [_P, _I]),
     "dfilter_profile_end": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)]),
     "closure_state_bytes": (_S, []),
@@ -686,3 +701,104 @@ class DFilter:
         dfilter_sgs_stress(self.h, _ptr(u), _ptr(ubar), _ptr(tau), _ptr(st) if st is not None else None,
                            _ptr(ws), ws.numel(), _stream())
         return ubar, tau, st
+
+
+# ---- the stress on an LES grid -----------------------------------------------
+
+def les_state_bytes(desc: LesDesc) -> int:
+    return lib.les_state_bytes(ctypes.byref(desc))
+
+
+def les_setup(desc, state_ptr, state_bytes, stream) -> _P:
+    h = _P()
+    _check(lib.les_setup(ctypes.byref(desc), state_ptr, state_bytes, stream, ctypes.byref(h)), "les_setup")
+    return h
+
+
+def les_stress(h, ubar_ptr, tau_ptr, ubar_les_ptr, T_ptr, stream):
+    _check(lib.les_stress(h, ubar_ptr, tau_ptr, ubar_les_ptr, T_ptr, stream), "les_stress")
+
+
+def les_commutation_workspace_bytes(h) -> int:
+    return lib.les_commutation_workspace_bytes(h)
+
+
+def les_commutation(h, g_ptr, out_ptr, ws_ptr, ws_bytes, stream):
+    _check(lib.les_commutation(h, g_ptr, out_ptr, ws_ptr, ws_bytes, stream), "les_commutation")
+
+
+def les_destroy(h):
+    lib.les_destroy(h)
+
+
+class LesGrid:
+    """The discretization operator from a DNS grid to an LES grid, with its
+    state on the current device."""
+
+    def __init__(self, nx, ny, nz, y, nx_les, ny_les, nz_les, y_les, device="cuda"):
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.shape = (int(nx), int(ny), int(nz))
+        self.les_shape = (int(nx_les), int(ny_les), int(nz_les))
+        self._y = np.ascontiguousarray(np.asarray(y, dtype=np.float64))
+        self._yl = np.ascontiguousarray(np.asarray(y_les, dtype=np.float64))
+        dp = ctypes.POINTER(ctypes.c_double)
+        desc = LesDesc(int(nx), int(ny), int(nz), self._y.ctypes.data_as(dp),
+                       int(nx_les), int(ny_les), int(nz_les), self._yl.ctypes.data_as(dp))
+        nbytes = les_state_bytes(desc)
+        if nbytes == 0:
+            raise ElesError(ELES_EINVAL, "les_state_bytes")
+        self.state = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.h = les_setup(desc, _ptr(self.state), nbytes, _stream())
+        self._ws = torch.empty(0, dtype=torch.uint8, device=dev)
+
+    @classmethod
+    def coarsened(cls, cfg, ratio, device="cuda"):
+        """The LES grid coarser by `ratio` in every direction (LES2, LES4), its
+        y nodes from the same stretching."""
+        from .synth import ygrid
+        y = ygrid(cfg.ny, cfg.ykind, cfg.stretch)
+        yl = ygrid((cfg.ny - 1) // ratio + 1, cfg.ykind, cfg.stretch)
+        return cls(cfg.nx, cfg.ny, cfg.nz, y, cfg.nx // ratio, len(yl), cfg.nz // ratio, yl, device)
+
+    # bound at class creation: module globals may already be gone when an
+    # object is collected at interpreter exit
+    def __del__(self, _destroy=lib.les_destroy):
+        h = getattr(self, "h", None)
+        if h:
+            _destroy(h)
+            self.h = None
+
+    def _check(self, t, n, shape):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device != self.device:
+            raise ValueError("fields must be contiguous float32 tensors on the grid's device")
+        if tuple(t.shape) != (n,) + shape:
+            raise ValueError(f"expected shape {(n,) + shape}, got {tuple(t.shape)}")
+
+    def stress(self, ubar: torch.Tensor, tau: torch.Tensor, ubar_les=None, T=None):
+        self._check(ubar, 3, self.shape)
+        self._check(tau, 6, self.shape)
+        if ubar_les is None:
+            ubar_les = torch.empty((3,) + self.les_shape, dtype=torch.float32, device=self.device)
+        if T is None:
+            T = torch.empty((6,) + self.les_shape, dtype=torch.float32, device=self.device)
+        self._check(ubar_les, 3, self.les_shape)
+        self._check(T, 6, self.les_shape)
+        les_stress(self.h, _ptr(ubar), _ptr(tau), _ptr(ubar_les), _ptr(T), _stream())
+        return ubar_les, T
+
+    def commutation(self, g: torch.Tensor) -> torch.Tensor:
+        """Device FP64 [1]: the commutation error of the DNS field g."""
+        if g.dim() == 4 and g.shape[0] == 1:
+            g = g[0]
+        if g.dtype != torch.float32 or not g.is_contiguous() or tuple(g.shape) != self.shape:
+            raise ValueError(f"g must be a contiguous float32 {self.shape} tensor")
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        nb = les_commutation_workspace_bytes(self.h)
+        if self._ws.numel() < nb:
+            self._ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        les_commutation(self.h, _ptr(g), _ptr(out), _ptr(self._ws), self._ws.numel(), _stream())
+        return out
+

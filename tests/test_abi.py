@@ -173,3 +173,37 @@ def test_dfilter_calls_on_null_handle_rejected(eles):
     assert eles.lib.dfilter_sgs_stress(None, 16, 16, 16, None, 16, 1 << 20, None) == eles.ELES_EINVAL
     assert eles.lib.dfilter_workspace_bytes(None, 3) == 0
     assert eles.lib.dfilter_sgs_workspace_bytes(None) == 0
+
+
+def _ldesc(eles, ny=9, nyl=5, y=None, yl=None, **over):
+    y = np.linspace(-1, 1, ny) if y is None else y
+    yl = np.linspace(-1, 1, nyl) if yl is None else yl
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    yl = np.ascontiguousarray(yl, dtype=np.float64)
+    kw = dict(nx=8, nz=6, nxl=4, nzl=3)
+    kw.update(over)
+    dp = ctypes.POINTER(ctypes.c_double)
+    d = eles.LesDesc(kw["nx"], len(y), kw["nz"], y.ctypes.data_as(dp), kw["nxl"], len(yl), kw["nzl"],
+                     yl.ctypes.data_as(dp))
+    return d, (y, yl)
+
+
+def test_les_descriptor_validation(eles):
+    d, keep = _ldesc(eles)
+    assert eles.les_state_bytes(d) > 0
+    for bad in (dict(nx=0), dict(nxl=0), dict(nzl=-1)):
+        d, keep = _ldesc(eles, **bad)
+        assert eles.les_state_bytes(d) == 0
+    for y, yl in ((np.linspace(-1, 0.9, 9), None), (np.linspace(-1, 1, 2), None),
+                  (None, np.linspace(-1.1, 1, 5)), (None, np.array([-1.0, 0.5, 0.2, 1.0])),
+                  (None, np.linspace(-1, 1, 2))):
+        d, keep = _ldesc(eles, y=y, yl=yl)
+        assert eles.les_state_bytes(d) == 0
+    d, keep = _ldesc(eles)
+    n = eles.les_state_bytes(d)
+    h = ctypes.c_void_p()
+    assert eles.lib.les_setup(ctypes.byref(d), None, n, None, ctypes.byref(h)) == eles.ELES_EINVAL
+    assert eles.lib.les_setup(ctypes.byref(d), 0x1000, n - 1, None, ctypes.byref(h)) == eles.ELES_ENOSPACE
+    assert eles.lib.les_stress(None, 16, 16, 16, 16, None) == eles.ELES_EINVAL
+    assert eles.lib.les_commutation(None, 16, 16, 16, 1 << 20, None) == eles.ELES_EINVAL
+    assert eles.lib.les_commutation_workspace_bytes(None) == 0
