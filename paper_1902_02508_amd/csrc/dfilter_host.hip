@@ -145,7 +145,8 @@ int32_t dfilter_setup(const eles_dfilter_desc *desc, void *state, size_t state_b
   v.cp = (float *)(s + p.off[D_CP]);
   v.inv = (float *)(s + p.off[D_INV]);
   v.prof = (float *)(s + p.off[D_PROF]);
-  if (hipMemcpyAsync(v.y64, f->y.data(), f->y.size() * sizeof(double), hipMemcpyHostToDevice, stream) !=
+  if (eles::dfilter_lds_limit(v) != hipSuccess ||
+      hipMemcpyAsync(v.y64, f->y.data(), f->y.size() * sizeof(double), hipMemcpyHostToDevice, stream) !=
           hipSuccess ||
       eles::launch_dsetup(v, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
     delete f;

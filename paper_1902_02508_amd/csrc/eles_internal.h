@@ -251,7 +251,9 @@ struct DView {
   float *op32;                  // [2][3][ny] -a^2 (sub, main, super) of the y difference
   float *cp, *inv;              // [2][hx + 1][ny][hz + 1] elimination factors
   float *prof;                  // [3][ny] m, M = F(m), F(m^2) - M^2
+  size_t ldsmax;                // largest table slice the LDS kernels may stage (bytes)
 };
+hipError_t dfilter_lds_limit(DView &v);   // sets v.ldsmax for the current device
 hipError_t launch_dsetup(const DView &v, hipStream_t s);
 // timed passes (ev: 2 events per pass, or null)
 enum { kDPassShift, kDPassXf, kDPassZf, kDPassY, kDPassZi, kDPassXi, kDPassEpi, kDPasses };

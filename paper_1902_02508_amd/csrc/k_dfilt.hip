@@ -301,6 +301,7 @@ __global__ void __launch_bounds__(256) k_dprof(DView v) {
 // along the middle axis (columns c contiguous, C = ny nz); LAST: R rows of
 // n contiguous values transformed along the row.
 struct DT {
+  size_t ldsmax;       // LDS-table kernels: largest slice (bytes)
   const float *tab;
   const float *in;
   float *out;
@@ -866,53 +867,85 @@ __global__ void __launch_bounds__(256) k_dsolve(DView v, const float *__restrict
   float *ya = out + (size_t)fa * fs + cbase;
   float *yb = out + (size_t)(two ? fb : fa) * fs + cbase;
   const int j0 = p, j1 = ny - 1 - p;
-  // forward elimination: r_j = (d_j - lo_j r_{j-1}) / den_j (lo_{j0} = 0)
-  float ra = 0.0f, rb = 0.0f;
-  for (int jb = j0; jb <= j1; jb += kCH) {
-    float da[kCH], db[kCH], ivj[kCH], lj[kCH], mj[kCH];
+  // forward elimination: r_j = (d_j - lo_j r_{j-1}) / den_j (lo_{j0} = 0);
+  // the next chunk of y values is requested before this one is eliminated
+  struct FC {
+    float da[kCH], db[kCH], iv[kCH], l[kCH], m[kCH];
+  };
+  auto fload = [&](int jb, FC &c) __attribute__((always_inline)) {
 #pragma unroll
-    for (int c = 0; c < kCH; ++c) {
-      const int jj = min(jb + c, j1);
-      da[c] = xa[(size_t)jj * nz];
-      db[c] = two ? xb[(size_t)jj * nz] : 0.0f;
-      ivj[c] = iv[(size_t)jj * nzc];
-      lj[c] = lo[jj];
-      mj[c] = m[jj];
+    for (int k = 0; k < kCH; ++k) {
+      const int jj = min(jb + k, j1);
+      c.da[k] = xa[(size_t)jj * nz];
+      c.db[k] = two ? xb[(size_t)jj * nz] : 0.0f;
+      c.iv[k] = iv[(size_t)jj * nzc];
+      c.l[k] = lo[jj];
+      c.m[k] = m[jj];
     }
+  };
+  float ra = 0.0f, rb = 0.0f;
+  auto fstep = [&](int jb, const FC &c) __attribute__((always_inline)) {
 #pragma unroll
-    for (int c = 0; c < kCH; ++c) {
-      if (jb + c > j1) break;
-      const int jj = jb + c;
-      ra = (da[c] - lj[c] * ra) * ivj[c];
+    for (int k = 0; k < kCH; ++k) {
+      if (jb + k > j1) break;
+      const int jj = jb + k;
+      ra = (c.da[k] - c.l[k] * ra) * c.iv[k];
       ya[(size_t)jj * nz] = ra;
       if (two) {
-        rb = ((db[c] + cj * mj[c] * da[c]) - lj[c] * rb) * ivj[c];
+        rb = ((c.db[k] + cj * c.m[k] * c.da[k]) - c.l[k] * rb) * c.iv[k];
         yb[(size_t)jj * nz] = rb;
       }
     }
-  }
-  // back substitution: x_j = r_j - c'_j x_{j+1} (c'_{j1} = 0)
-  float xa1 = 0.0f, xb1 = 0.0f;
-  for (int jt = j1; jt >= j0; jt -= kCH) {
-    float r1[kCH], r2[kCH], cpj[kCH], Mj[kCH];
-#pragma unroll
-    for (int c = 0; c < kCH; ++c) {
-      const int jj = max(jt - c, j0);
-      r1[c] = ya[(size_t)jj * nz];
-      r2[c] = two ? yb[(size_t)jj * nz] : 0.0f;
-      cpj[c] = cp[(size_t)jj * nzc];
-      Mj[c] = M[jj];
+  };
+  {
+    FC A, B;
+    fload(j0, A);
+    for (int jb = j0; jb <= j1; jb += 2 * kCH) {
+      fload(jb + kCH, B);
+      fstep(jb, A);
+      if (jb + kCH > j1) break;
+      fload(jb + 2 * kCH, A);
+      fstep(jb + kCH, B);
     }
+  }
+  // back substitution: x_j = r_j - c'_j x_{j+1} (c'_{j1} = 0); a chunk's
+  // r values are read before the rows below it are overwritten
+  struct BC {
+    float r1[kCH], r2[kCH], cp[kCH], M[kCH];
+  };
+  auto bload = [&](int jt, BC &c) __attribute__((always_inline)) {
 #pragma unroll
-    for (int c = 0; c < kCH; ++c) {
-      if (jt - c < j0) break;
-      const int jj = jt - c;
-      xa1 = r1[c] - cpj[c] * xa1;
+    for (int k = 0; k < kCH; ++k) {
+      const int jj = max(jt - k, j0);
+      c.r1[k] = ya[(size_t)jj * nz];
+      c.r2[k] = two ? yb[(size_t)jj * nz] : 0.0f;
+      c.cp[k] = cp[(size_t)jj * nzc];
+      c.M[k] = M[jj];
+    }
+  };
+  float xa1 = 0.0f, xb1 = 0.0f;
+  auto bstep = [&](int jt, const BC &c) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < kCH; ++k) {
+      if (jt - k < j0) break;
+      const int jj = jt - k;
+      xa1 = c.r1[k] - c.cp[k] * xa1;
       ya[(size_t)jj * nz] = xa1;
       if (two) {
-        xb1 = r2[c] - cpj[c] * xb1;
-        yb[(size_t)jj * nz] = xb1 - cj * Mj[c] * xa1;
+        xb1 = c.r2[k] - c.cp[k] * xb1;
+        yb[(size_t)jj * nz] = xb1 - cj * c.M[k] * xa1;
       }
+    }
+  };
+  {
+    BC A, B;
+    bload(j1, A);
+    for (int jt = j1; jt >= j0; jt -= 2 * kCH) {
+      bload(jt - kCH, B);
+      bstep(jt, A);
+      if (jt - kCH < j0) break;
+      bload(jt - 2 * kCH, A);
+      bstep(jt - kCH, B);
     }
   }
   if (p) {
@@ -1145,6 +1178,7 @@ unsigned grid_of(long work, int per) { return (unsigned)((work + per - 1) / per)
 
 DT targs(const DView &v, bool x, const float *tab, const float *in, float *out, int nb) {
   DT a;
+  a.ldsmax = v.ldsmax;
   a.tab = tab;
   a.in = in;
   a.out = out;
@@ -1159,8 +1193,6 @@ DT targs(const DView &v, bool x, const float *tab, const float *in, float *out, 
   return a;
 }
 
-// the LDS-table kernels cover axes whose table slice fits in 64 KB
-constexpr size_t kDLdsMax = 65536;
 size_t fwd_slice_bytes(const DAxis &ax) { return (size_t)kDTS * ax.ks4 * 1024; }
 size_t inv_slice_bytes(const DAxis &ax) { return (size_t)2 * kDTI * ax.ks4 * 1024; }
 long host_data_groups(const DT &a, bool last) {
@@ -1172,7 +1204,7 @@ int blocks_per_group(int ngroups) { return max(1, 256 / ngroups); }
 template <bool LAST, bool PROD>
 void fwd(const DT &a, hipStream_t s) {
   const size_t lds = fwd_slice_bytes(a.ax);
-  if (lds <= kDLdsMax) {
+  if (lds <= a.ldsmax) {
     const int nbt = blocks_per_group(a.ax.gf);
     k_dfwd_lds<LAST, PROD><<<nbt * a.ax.gf, 64 * kDWaves, lds, s>>>(a, nbt);
   } else {
@@ -1182,7 +1214,7 @@ void fwd(const DT &a, hipStream_t s) {
 template <bool LAST>
 void inv(const DT &a, hipStream_t s) {
   const size_t lds = inv_slice_bytes(a.ax);
-  if (lds <= kDLdsMax) {
+  if (lds <= a.ldsmax) {
     const int nbt = blocks_per_group(a.ax.gi);
     k_dinv_lds<LAST><<<nbt * a.ax.gi, 64 * kDWaves, lds, s>>>(a, nbt);
   } else {
@@ -1226,6 +1258,26 @@ hipError_t run_filter(const DView &v, const float *in, int nf, unsigned pmask, f
 }
 
 }  // namespace
+
+// The LDS-table kernels stage up to the device's per-block LDS: the
+// dynamic-LDS limit of each instance is raised to it (64 KB without).
+hipError_t dfilter_lds_limit(DView &v) {
+  int dev = 0, bytes = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return hipErrorUnknown;
+  v.ldsmax = 65536;
+  if (bytes > 65536) {
+    const void *k[] = {(const void *)k_dfwd_lds<false, false>, (const void *)k_dfwd_lds<false, true>,
+                       (const void *)k_dfwd_lds<true, false>, (const void *)k_dinv_lds<false>,
+                       (const void *)k_dinv_lds<true>};
+    for (const void *f : k)
+      if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
+        return hipSuccess;   // keep 64 KB
+    v.ldsmax = (size_t)bytes;
+  }
+  return hipSuccess;
+}
 
 hipError_t launch_dsetup(const DView &v, hipStream_t s) {
   for (int x = 0; x < 2; ++x) {

@@ -5,9 +5,11 @@ Inputs are the seeded synthetic channel fields rounded to FP32; the oracle
 evaluates the same rounded values in FP64. Tolerances: the filtered fields
 to 2e-6 relative L2 (dense FP32 transforms of at most a few hundred terms
 and a diagonally dominant tridiagonal solve), the stress per component to
-max(1e-5, 8 kappa 2^-24) with kappa = |F(u_i' u_j')| / |tau_ij| (u1 shifted
-by its plane mean), the rounding of the larger term carried into the
-difference.
+max(1e-5, kappa (8 + 2 sqrt(nx/2) + 2 sqrt(nz/2)) 2^-24) with
+kappa = |F(u_i' u_j')| / |tau_ij| (u1 shifted by its plane mean): the
+rounding of the larger term carried into the difference, a folded forward
+and inverse transform of n/2 terms each per periodic axis (rounding of a
+K-term FP32 sum ~ sqrt(K) 2^-24) and a few products.
 """
 import math
 
@@ -47,6 +49,8 @@ GRIDS = [
     # long axes: several cosine tile groups, tables read from memory
     ("long_x", "tiny", dict(nx=270, nz=12, ny=9, lx=8.0)),
     ("long_z", "tiny", dict(nx=10, nz=300, ny=7, lz=9.0)),
+    # 512 nodes: table slices of 112 / 128 KB staged in LDS where the device allows
+    ("x512", "tiny", dict(nx=512, nz=16, ny=9, lx=16.0)),
 ]
 
 
@@ -76,11 +80,12 @@ def _tolerances(u, ops, tau):
     u = u.astype(np.float64)
     v = u.copy()
     v[0] -= R.plane_mean(u[0])[None, :, None]
+    depth = 8 + 2 * math.sqrt(ops.nx / 2) + 2 * math.sqrt(ops.nz / 2)
     tol = []
     for k, (i, j) in enumerate(D.PAIRS):
         big = D.dfilt(v[i] * v[j], D.PARITY[i] * D.PARITY[j], ops)
         kappa = math.sqrt(np.sum(big ** 2) / np.sum(tau[k] ** 2))
-        tol.append(max(1e-5, 8 * kappa * 2.0 ** -24))
+        tol.append(max(1e-5, kappa * depth * 2.0 ** -24))
     return tol
 
 
@@ -90,6 +95,7 @@ SGS = [
     ("odd_sizes", "tiny", dict(nx=10, nz=13, ny=21, ykind="tanh", stretch=2.0), 1),
     ("dns192_small", "dns192", dict(nx=40, nz=36, ny=33), 2),
     ("long_xz", "tiny", dict(nx=264, nz=290, ny=7, lx=8.0, lz=9.0), 5),
+    ("x512_z512", "tiny", dict(nx=512, nz=512, ny=5, lx=16.0, lz=16.0), 6),
     ("dns192", "dns192", dict(), 3),
 ]
 
