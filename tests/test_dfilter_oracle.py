@@ -263,3 +263,30 @@ def test_eq9_extension_violates_eq11_for_the_gaussian_too():
     bad = R.filt(u[1], +1, ops)
     assert np.max(np.abs(good[:, [0, -1], :])) < 1e-14
     assert _rms(bad[:, 0, :]) > 0.1 * _rms(bad[:, 1, :])
+
+
+@pytest.mark.parametrize("parity,nth,sx,sz", [(1, 3, 5, 2), (-1, 2, 3, 4)])
+def test_eigenmode_on_stretched_y(parity, nth, sx, sz):
+    """On a stretched y grid: phi with D phi = lam phi (numpy's eigen-solver on
+    the tridiagonal written from its definition) times a Fourier mode is
+    divided by 1 + a^2 (kx^2 + kz^2) - a^2 lam by the filter and multiplied by
+    it by the operator."""
+    cfg = synth.config("tiny", nx=16, nz=12, ny=33)
+    ops = D.DOperators.from_config(cfg)
+    y = synth.ygrid(cfg.ny, cfg.ykind, cfg.stretch)
+    A = _fd_matrix(y, parity)
+    if parity < 0:
+        A = A[1:-1, 1:-1]
+    lam, vec = np.linalg.eig(A)
+    k = np.argsort(-lam.real)[nth]
+    phi = np.real(vec[:, k])
+    if parity < 0:
+        phi = np.concatenate([[0.0], phi, [0.0]])
+    a = 0.1
+    kx, kz = 2 * math.pi * sx / cfg.lx, 2 * math.pi * sz / cfg.lz
+    g = 1.0 + a * a * (kx * kx + kz * kz) - a * a * lam[k].real
+    x = np.arange(cfg.nx) * cfg.lx / cfg.nx
+    z = np.arange(cfg.nz) * cfg.lz / cfg.nz
+    u = np.cos(kx * x[:, None, None] + kz * z[None, None, :] + 0.25) * phi[None, :, None]
+    assert np.max(np.abs(D.dfilt(u, parity, ops) - u / g)) < 1e-13
+    assert np.max(np.abs(D.laplacian_apply(u, parity, ops) - u * g)) < 1e-11

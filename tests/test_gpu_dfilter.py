@@ -195,3 +195,69 @@ def test_dfilter_errors_match_oracle(E, label, base, over):
     assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-10
     same = _host(f.errors(_dev(u), _dev(u), 1.0, 1.0))
     assert np.all(same == 0.0)
+
+
+# ---- full size: an eigenmode of the operator (closed form at any size)
+
+def _eigenmode(cfg, parity, nth):
+    """phi(y) with D phi = lam phi for the reflected three-point difference of
+    the given parity (numpy's eigen-solver on the ny x ny tridiagonal), the
+    nth smoothest mode; odd: zero on the walls."""
+    y = synth.ygrid(cfg.ny, cfg.ykind, cfg.stretch)
+    lo, di, hi = D.second_difference(y, parity)
+    m = len(di)
+    A = np.diag(di) + np.diag(lo[1:], -1) + np.diag(hi[:-1], 1)
+    lam, vec = np.linalg.eig(A)
+    order = np.argsort(-lam.real)                     # smallest |lambda| first (lambda <= 0)
+    k = order[nth]
+    phi = np.real(vec[:, k])
+    phi /= np.max(np.abs(phi))
+    if parity < 0:
+        phi = np.concatenate([[0.0], phi, [0.0]])
+    return y, phi, float(lam[k].real)
+
+
+@pytest.mark.parametrize("wl", ["dns512", "dns1024"])
+@pytest.mark.parametrize("parity,nth,sx,sz", [(1, 3, 5, 2), (-1, 2, 3, 4)])
+def test_dfilter_eigenmode_full_size(E, wl, parity, nth, sx, sz):
+    """F(cos(kx x + kz z) phi(y)) = that / (1 + a^2 (kx^2 + kz^2) - a^2 lam), and the
+    inverse multiplies by the same factor; the field is formed on the device.
+    Tolerance of the filter: max(2e-6, 4 (sqrt(nx/2) + sqrt(nz/2)) 2^-24), the
+    folded transforms' sum lengths. The inverse applies the operator to
+    coefficients that carry FP32 rounding, which it amplifies by up to its
+    infinity norm (large next to clustered wall nodes): 8 2^-24 ||A||."""
+    import torch
+    cfg = synth.config(wl)
+    y, phi, lam = _eigenmode(cfg, parity, nth)
+    a = 0.1
+    kx, kz = 2 * math.pi * sx / cfg.lx, 2 * math.pi * sz / cfg.lz
+    g = 1.0 + a * a * (kx * kx + kz * kz) - a * a * lam
+    dev = torch.device("cuda")
+    x = torch.arange(cfg.nx, device=dev, dtype=torch.float64) * (cfg.lx / cfg.nx)
+    z = torch.arange(cfg.nz, device=dev, dtype=torch.float64) * (cfg.lz / cfg.nz)
+    xz = torch.cos(kx * x[:, None] + kz * z[None, :] + 0.25)                 # [nx, nz]
+    ph = torch.from_numpy(phi).to(dev)
+    u = (xz[:, None, :] * ph[None, :, None]).to(torch.float32).unsqueeze(0).contiguous()
+    f = E.DFilter.from_config(cfg)
+    w = torch.from_numpy(R.trapezoid(y)).to(dev)[None, :, None]
+    tol = max(2e-6, 4 * (math.sqrt(cfg.nx / 2) + math.sqrt(cfg.nz / 2)) * 2.0 ** -24)
+
+    def rel(a_, b_):
+        d = a_[0].double() - b_
+        return math.sqrt(float((w * d * d).sum()) / float((w * b_ * b_).sum()))
+
+    ops = D.DOperators.from_config(cfg)
+    lo, di, hi = D.second_difference(ops.y, 1)
+    norm = 1.0 + a * a * (np.max(ops.k2) + np.max(np.abs(lo) + np.abs(di) + np.abs(hi)))
+    tol_inv = max(tol, 8 * 2.0 ** -24 * norm)
+    out = f.filter_fields(u, [parity])
+    e1 = rel(out, u[0].double() / g)
+    back = f.inverse(u, [parity])
+    e2 = rel(back, u[0].double() * g)
+    print(wl, parity, f"filter {e1:.2e} (tol {tol:.1e}) inverse {e2:.2e} (tol {tol_inv:.1e}, "
+          f"operator norm {norm:.0f})", flush=True)
+    assert e1 < tol and e2 < tol_inv
+    if parity < 0:
+        assert float(out[0][:, [0, -1], :].abs().max()) == 0.0
+    del out, back, u
+    torch.cuda.empty_cache()
