@@ -43,6 +43,9 @@ def parse():
     p.add_argument("--xz", default="matrix", choices=["matrix", "vector"],
                    help="x/z pass on the matrix cores (where it covers the grid) or the vector units")
     p.add_argument("--snapshots", type=int, default=4)
+    p.add_argument("--skip-extras", action="store_true",
+                   help="time only the stress (no LES-grid, inverse-filter or error measurements): "
+                        "for profiler runs whose per-kernel figures must cover the stress alone")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the oracle CPU baseline (0 disables it)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -195,7 +198,7 @@ def les_grid_measure(cfg, eles, torch, ubar, tau, steps):
     return out
 
 
-def main_differential(a):
+def run_differential(a):
     import numpy as np
     import torch
     from paper_1902_02508_amd import counters, eles, synth
@@ -244,32 +247,9 @@ def main_differential(a):
     dom = max(model, key=lambda k: prof[k][0])
     passes = {k: {"us_avg": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in prof.items()}
 
-    # the inverse filter of the three filtered velocities, and the error
-    # measures of eqs. (13)-(15) against the unfiltered field
-    back = torch.empty_like(ubar[0])
-    eles.dfilter_profile_begin(f.h, a.steps)
-    for i in range(a.steps):
-        f.inverse(ubar[i % ns], [1, -1, 1], out=back)
-    prof_i = eles.dfilter_profile_end(f.h)
-    model_i = dfilter_pass_model(cfg, nf=3, products=False)
-    roofs_i = dfilter_rooflines(cfg, model_i, prof_i, None, counters)
-    dom_i = max(model_i, key=lambda k: prof_i[k][0])
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    f.errors(back, us[0], 1.0, 1.0)
-    e0.record()
-    for i in range(a.steps):
-        err = f.errors(back, us[(a.steps - 1) % ns], 1.0, 1.0)
-    e1.record()
-    torch.cuda.synchronize()
-    t_err = e0.elapsed_time(e1) / a.steps * 1e-3
-    err_bytes = 24.0 * cfg.points   # two velocity fields read once
-    inverse = {"us_per_call": sum(1e3 * ms / max(n, 1) for ms, n in prof_i.values()),
-               "passes": {k: round(1e3 * ms / max(n, 1), 2) for k, (ms, n) in prof_i.items() if n},
-               "roofline": roofs_i[dom_i], "fields": 3,
-               "round_trip_errors_eq13_15": [float(v) for v in err.cpu().numpy()]}
-    errors = {"us_per_call": 1e6 * t_err, "bytes": err_bytes,
-              "roofline": {"bound": "hbm", "achieved": err_bytes / t_err / 1e9, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": err_bytes / t_err / 1e9 / HBM_PEAK_GBS}}
+    inverse, errors = None, None
+    if not a.skip_extras:
+        inverse, errors = dfilter_extras(cfg, eles, torch, f, us, ubar, a.steps, counters)
 
     cpu = None
     parity = None
@@ -283,7 +263,42 @@ def main_differential(a):
         gt = tau[0].cpu().numpy().astype(np.float64)
         parity = max([R.rel_l2(gu[k], rub[k], yv) for k in range(3)] +
                      [R.rel_l2(gt[k], rtau[k], yv) for k in range(6)])
+    return cfg, value, ms_per_step, ns, roofs, dom, passes, cpu, parity, inverse, errors
 
+
+def dfilter_extras(cfg, eles, torch, f, us, ubar, steps, counters):
+    """The inverse filter of the three filtered velocities and the error
+    measures of eqs. (13)-(15) against the unfiltered field, timed."""
+    ns = len(us)
+    back = torch.empty_like(ubar[0])
+    eles.dfilter_profile_begin(f.h, steps)
+    for i in range(steps):
+        f.inverse(ubar[i % ns], [1, -1, 1], out=back)
+    prof_i = eles.dfilter_profile_end(f.h)
+    model_i = dfilter_pass_model(cfg, nf=3, products=False)
+    roofs_i = dfilter_rooflines(cfg, model_i, prof_i, None, counters)
+    dom_i = max(model_i, key=lambda k: prof_i[k][0])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f.errors(back, us[0], 1.0, 1.0)
+    e0.record()
+    for i in range(steps):
+        err = f.errors(back, us[(steps - 1) % ns], 1.0, 1.0)
+    e1.record()
+    torch.cuda.synchronize()
+    t_err = e0.elapsed_time(e1) / steps * 1e-3
+    err_bytes = 24.0 * cfg.points   # two velocity fields read once
+    inverse = {"us_per_call": sum(1e3 * ms / max(n, 1) for ms, n in prof_i.values()),
+               "passes": {k: round(1e3 * ms / max(n, 1), 2) for k, (ms, n) in prof_i.items() if n},
+               "roofline": roofs_i[dom_i], "fields": 3,
+               "round_trip_errors_eq13_15": [float(v) for v in err.cpu().numpy()]}
+    errors = {"us_per_call": 1e6 * t_err, "bytes": err_bytes,
+              "roofline": {"bound": "hbm", "achieved": err_bytes / t_err / 1e9, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": err_bytes / t_err / 1e9 / HBM_PEAK_GBS}}
+    return inverse, errors
+
+
+def main_differential(a):
+    cfg, value, ms_per_step, ns, roofs, dom, passes, cpu, parity, inverse, errors = run_differential(a)
     line = {
         "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step,
@@ -395,7 +410,7 @@ def main():
     dom = max(("xz", "y"), key=lambda k: prof[k][0])
     roof = roofs[dom]
 
-    les = les_grid_measure(cfg, eles, torch, ubar, tau, a.steps)
+    les = None if a.skip_extras else les_grid_measure(cfg, eles, torch, ubar, tau, a.steps)
 
     cpu = None
     parity = None
