@@ -164,15 +164,19 @@ int32_t sgs_stress(eles_filter f, const float *u, float *ubar, float *tau,
                    double *stats, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Per-pass GPU timing of later sgs_stress / filter_fields calls on this
- * handle, with HIP events recorded on the call's stream around every
- * kernel. Passes: 0 shift profile and correction operators, 1 x/z pass,
- * 2 y pass, 3 plane statistics. filter_profile_begin creates events for up
- * to max_calls calls (host-side HIP events; no device memory). After the
- * timed calls, filter_profile_end waits for the last event and returns, per
- * pass, the summed milliseconds and the number of launches timed, then
- * releases the events. Errors: EINVAL, EHIP. */
+ * handle, with HIP events recorded on the call's stream around the kernels
+ * of the passes selected by pass_mask (bit p times pass p). Passes: 0 shift
+ * profile and correction operators, 1 x/z pass, 2 y pass, 3 plane
+ * statistics. Each event pair adds a few microseconds between kernels, so
+ * a throughput measurement times only the passes it needs.
+ * filter_profile_begin creates events for up to max_calls calls (host-side
+ * HIP events; no device memory). After the timed calls, filter_profile_end
+ * waits for the last event and returns, per pass, the summed milliseconds
+ * and the number of launches timed (zero for passes not selected), then
+ * releases the events. Errors: EINVAL (pass_mask zero or naming a pass
+ * past ELES_NPASS - 1), EHIP. */
 #define ELES_NPASS 4
-int32_t filter_profile_begin(eles_filter f, int32_t max_calls);
+int32_t filter_profile_begin(eles_filter f, int32_t max_calls, uint32_t pass_mask);
 int32_t filter_profile_end(eles_filter f, double *ms /* [ELES_NPASS] */,
                            int32_t *launches /* [ELES_NPASS] */);
 
@@ -260,7 +264,8 @@ int32_t dfilter_errors(eles_dfilter f, const float *les, const float *dns, doubl
 
 /* Per-pass GPU timing of later dfilter_sgs_stress / dfilter_fields /
  * dfilter_inverse calls on this handle, with HIP events recorded on the
- * call's stream around every pass: 0 shift profile, 1 x forward transform (with the products), 2 z
+ * call's stream around the passes selected by pass_mask (bit p times pass
+ * p; EINVAL when zero or naming a pass past ELES_DNPASS - 1): 0 shift profile, 1 x forward transform (with the products), 2 z
  * forward transform, 3 y solves (dfilter_inverse: the y operator), 4 z
  * inverse transform, 5 x inverse transform, 6 stress epilogue and plane
  * statistics (dfilter_fields and dfilter_inverse time passes 1 .. 5). dfilter_profile_begin creates events for up to max_calls
@@ -269,7 +274,7 @@ int32_t dfilter_errors(eles_dfilter f, const float *les, const float *dns, doubl
  * number of timed launches, then releases the events. Errors: EINVAL,
  * EHIP. */
 #define ELES_DNPASS 7
-int32_t dfilter_profile_begin(eles_dfilter f, int32_t max_calls);
+int32_t dfilter_profile_begin(eles_dfilter f, int32_t max_calls, uint32_t pass_mask);
 int32_t dfilter_profile_end(eles_dfilter f, double *ms /* [ELES_DNPASS] */,
                             int32_t *launches /* [ELES_DNPASS] */);
 

@@ -16,6 +16,7 @@ struct eles_dfilter_s {
   size_t npts;
   // timing: events [call][pass][start, stop], used flags [call][pass]
   int prof_max = 0, prof_calls = 0;
+  unsigned prof_mask = 0;   // passes timed; the events of the others stay null
   std::vector<hipEvent_t> ev;
   std::vector<char> used;
 };
@@ -31,7 +32,7 @@ const hipEvent_t *call_events(eles_dfilter_s *f, bool sgs) {
   if (f->prof_max == 0 || f->prof_calls >= f->prof_max) return nullptr;
   const size_t base = (size_t)f->prof_calls * ELES_DNPASS;
   for (int p = 0; p < ELES_DNPASS; ++p)
-    f->used[base + p] = sgs || (p != eles::kDPassShift && p != eles::kDPassEpi);
+    f->used[base + p] = ((f->prof_mask >> p) & 1u) && (sgs || (p != eles::kDPassShift && p != eles::kDPassEpi));
   ++f->prof_calls;
   return f->ev.data() + 2 * base;
 }
@@ -42,6 +43,7 @@ void release_events(eles_dfilter_s *f) {
   f->ev.clear();
   f->used.clear();
   f->prof_max = f->prof_calls = 0;
+  f->prof_mask = 0;
 }
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 bool overlap(const void *a, size_t na, const void *b, size_t nb) {
@@ -209,17 +211,19 @@ int32_t dfilter_sgs_stress(eles_dfilter f, const float *u, float *ubar, float *t
              : ELES_EHIP;
 }
 
-int32_t dfilter_profile_begin(eles_dfilter f, int32_t max_calls) {
-  if (!f || max_calls < 1 || max_calls > (1 << 20)) return ELES_EINVAL;
+int32_t dfilter_profile_begin(eles_dfilter f, int32_t max_calls, uint32_t pass_mask) {
+  if (!f || max_calls < 1 || max_calls > (1 << 20) || pass_mask == 0 || (pass_mask >> ELES_DNPASS))
+    return ELES_EINVAL;
   release_events(f);
   const size_t n = (size_t)max_calls * ELES_DNPASS;
   f->ev.assign(2 * n, nullptr);
   f->used.assign(n, 0);
-  for (auto &e : f->ev)
-    if (hipEventCreate(&e) != hipSuccess) {
+  for (size_t i = 0; i < f->ev.size(); ++i)
+    if (((pass_mask >> ((i / 2) % ELES_DNPASS)) & 1u) && hipEventCreate(&f->ev[i]) != hipSuccess) {
       release_events(f);
       return ELES_EHIP;
     }
+  f->prof_mask = pass_mask;
   f->prof_max = max_calls;
   f->prof_calls = 0;
   return ELES_OK;

@@ -27,7 +27,8 @@ struct eles_filter_s {
   eles::XzmPlan xzm;
   // per-pass event timing
   int prof_max = 0, prof_calls = 0;
-  std::vector<hipEvent_t> ev;   // [call][pass][start, stop]
+  unsigned prof_mask = 0;       // passes timed
+  std::vector<hipEvent_t> ev;   // [call][pass][start, stop]; null for passes not timed
   std::vector<int> used;        // [call][pass]
 };
 
@@ -305,7 +306,7 @@ eles::XzArgs xz_args(const eles_filter_s *f) {
 // Launch one pass, bracketed by timing events when profiling is on.
 template <class F>
 hipError_t timed(eles_filter_s *f, int pass, hipStream_t s, F &&launch) {
-  const bool on = f->prof_max > 0 && f->prof_calls < f->prof_max;
+  const bool on = f->prof_max > 0 && f->prof_calls < f->prof_max && ((f->prof_mask >> pass) & 1u);
   const size_t k = ((size_t)f->prof_calls * ELES_NPASS + pass);
   if (on && hipEventRecord(f->ev[2 * k], s) != hipSuccess) return hipErrorUnknown;
   hipError_t e = launch();
@@ -327,6 +328,7 @@ void release_events(eles_filter_s *f) {
   f->ev.clear();
   f->used.clear();
   f->prof_max = f->prof_calls = 0;
+  f->prof_mask = 0;
 }
 
 }  // namespace
@@ -538,17 +540,19 @@ int32_t sgs_stress(eles_filter f, const float *u, float *ubar, float *tau, doubl
   return ELES_OK;
 }
 
-int32_t filter_profile_begin(eles_filter f, int32_t max_calls) {
-  if (!f || max_calls < 1 || max_calls > (1 << 20)) return ELES_EINVAL;
+int32_t filter_profile_begin(eles_filter f, int32_t max_calls, uint32_t pass_mask) {
+  if (!f || max_calls < 1 || max_calls > (1 << 20) || pass_mask == 0 || (pass_mask >> ELES_NPASS))
+    return ELES_EINVAL;
   release_events(f);
   const size_t n = (size_t)max_calls * ELES_NPASS;
   f->ev.assign(2 * n, nullptr);
   f->used.assign(n, 0);
-  for (auto &e : f->ev)
-    if (hipEventCreate(&e) != hipSuccess) {
+  for (size_t i = 0; i < f->ev.size(); ++i)
+    if (((pass_mask >> ((i / 2) % ELES_NPASS)) & 1u) && hipEventCreate(&f->ev[i]) != hipSuccess) {
       release_events(f);
       return ELES_EHIP;
     }
+  f->prof_mask = pass_mask;
   f->prof_max = max_calls;
   f->prof_calls = 0;
   return ELES_OK;

@@ -1226,9 +1226,9 @@ void inv(const DT &a, hipStream_t s) {
 // in -> w1, z forward w1 -> w0, solve w0 -> w1, z inverse w1 -> w0, x
 // inverse w0 -> out; out may be w1)
 // Timing events of one call: ev[2 p] before and ev[2 p + 1] after pass p
-// (DPass), or null.
+// (DPass), or null; a null entry leaves that pass untimed.
 void mark(const hipEvent_t *ev, int idx, hipStream_t s) {
-  if (ev) (void)hipEventRecord(ev[idx], s);
+  if (ev && ev[idx]) (void)hipEventRecord(ev[idx], s);
 }
 
 template <bool SGS, bool APPLY = false>

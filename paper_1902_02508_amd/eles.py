@@ -82,7 +82,7 @@ _SIG = {
     "sgs_workspace_bytes": (_S, [_P]),
     "filter_fields": (_I, [_P, _P, _I, _P, _P, _P, _S, _P]),
     "sgs_stress": (_I, [_P, _P, _P, _P, _P, _P, _S, _P]),
-    "filter_profile_begin": (_I, [_P, _I]),
+    "filter_profile_begin": (_I, [_P, _I, ctypes.c_uint32]),
     "filter_profile_end": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)]),
     "filter_destroy": (None, [_P]),
     "dfilter_state_bytes": (_S, [ctypes.POINTER(DFilterDesc)]),
@@ -101,7 +101,7 @@ _SIG = {
     "les_commutation_workspace_bytes": (_S, [_P]),
     "les_commutation": (_I, [_P, _P, _P, _P, _S, _P]),
     "les_destroy": (None, [_P]),
-    "dfilter_profile_begin": (_I, [_P, _I]),
+    "dfilter_profile_begin": (_I, [_P, _I, ctypes.c_uint32]),
     "dfilter_profile_end": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)]),
     "closure_state_bytes": (_S, []),
     "closure_create": (_I, [_P, _S, _P, _P, _P, ctypes.POINTER(_P)]),
@@ -197,8 +197,14 @@ NPASS = 4
 PASS_NAMES = ("shift", "xz", "y", "stats")
 
 
-def filter_profile_begin(h, max_calls: int):
-    _check(lib.filter_profile_begin(h, max_calls), "filter_profile_begin")
+def _pass_mask(passes, npass):
+    return (1 << npass) - 1 if passes is None else sum(1 << int(p) for p in set(passes))
+
+
+def filter_profile_begin(h, max_calls: int, passes=None):
+    """Time the passes listed (indices into PASS_NAMES; all when None) of
+    the next max_calls calls."""
+    _check(lib.filter_profile_begin(h, max_calls, _pass_mask(passes, NPASS)), "filter_profile_begin")
 
 
 def filter_profile_end(h):
@@ -584,8 +590,10 @@ DNPASS = 7
 DPASS_NAMES = ("shift", "x_fwd", "z_fwd", "y_solve", "z_inv", "x_inv", "epilogue")
 
 
-def dfilter_profile_begin(h, max_calls: int):
-    _check(lib.dfilter_profile_begin(h, max_calls), "dfilter_profile_begin")
+def dfilter_profile_begin(h, max_calls: int, passes=None):
+    """Time the passes listed (indices into DPASS_NAMES; all when None) of
+    the next max_calls calls."""
+    _check(lib.dfilter_profile_begin(h, max_calls, _pass_mask(passes, DNPASS)), "dfilter_profile_begin")
 
 
 def dfilter_profile_end(h):

@@ -261,3 +261,24 @@ def test_dfilter_eigenmode_full_size(E, wl, parity, nth, sx, sz):
         assert float(out[0][:, [0, -1], :].abs().max()) == 0.0
     del out, back, u
     torch.cuda.empty_cache()
+
+
+def test_dfilter_profile_pass_mask(E):
+    """Timing the x forward transform alone leaves the other passes untimed
+    and the outputs unchanged; an empty mask or a pass past the last is
+    rejected."""
+    cfg = synth.config("tiny", nx=24, nz=20, ny=17)
+    y, u = synth.make_snapshot(cfg, 3)
+    f = E.DFilter.from_config(cfg)
+    du = _dev(u)
+    ref = [_host(t) for t in f.sgs_stress(du)]
+    E.dfilter_profile_begin(f.h, 2, passes=[E.DPASS_NAMES.index("x_fwd")])
+    for _ in range(2):
+        out = [_host(t) for t in f.sgs_stress(du)]
+    prof = E.dfilter_profile_end(f.h)
+    for p, q in zip(ref, out):
+        assert np.array_equal(p, q)
+    assert prof["x_fwd"][1] == 2 and prof["x_fwd"][0] > 0.0
+    assert all(n == 0 for k, (ms, n) in prof.items() if k != "x_fwd")
+    for mask in (0, 1 << E.DNPASS):
+        assert E.lib.dfilter_profile_begin(f.h, 2, mask) == E.ELES_EINVAL

@@ -255,3 +255,23 @@ def test_sgs_reduced_precision_y_pass(E, mode, tol):
     errs = [_rel(ub[k], rub[k], y) for k in range(3)] + [_rel(tau[k], rtau[k], y) for k in range(6)]
     print(mode, " ".join(f"{e:.2e}" for e in errs), flush=True)
     assert max(errs) < tol
+
+
+def test_profile_pass_mask_times_only_the_selected_passes(E):
+    """Timing one pass leaves the others untimed and the outputs unchanged;
+    an empty mask or a pass past the last is rejected."""
+    cfg = synth.config("dns192", nx=48, nz=64)
+    y, u = synth.make_snapshot(cfg, 6)
+    f = E.Filter.from_config(cfg)
+    du = _dev(u)
+    ref = [_host(t) for t in f.sgs_stress(du)]
+    E.filter_profile_begin(f.h, 3, passes=[E.PASS_NAMES.index("y")])
+    for _ in range(3):
+        out = [_host(t) for t in f.sgs_stress(du)]
+    prof = E.filter_profile_end(f.h)
+    for p, q in zip(ref, out):
+        assert np.array_equal(p, q)
+    assert prof["y"][1] == 3 and prof["y"][0] > 0.0
+    assert all(n == 0 for k, (ms, n) in prof.items() if k != "y")
+    for mask in (0, 1 << E.NPASS):
+        assert E.lib.filter_profile_begin(f.h, 3, mask) == E.ELES_EINVAL
