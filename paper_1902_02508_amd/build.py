@@ -28,6 +28,16 @@ FLAGS = [
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 
+# per-source additions. The perceptron kernels keep matrix-core results in
+# ordinary VGPRs (the inference epilogue reads every accumulator, and the
+# accumulator-register form costs one copy per value), and run with IEEE
+# mode off: the GELU's min / max then take the matrix-core results as they
+# are, where IEEE mode makes the compiler canonicalize each one first. The
+# perceptron has no NaN inputs and tests none.
+EXTRA = {
+    "k_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form", "-mno-amdgpu-ieee", "-fno-honor-nans"],
+}
+
 
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
@@ -57,7 +67,8 @@ def build(verbose: bool = False) -> str:
         for src in sources():
             obj = os.path.join(BUILD_DIR, os.path.basename(src)[:-4] + ".o")
             objs.append(obj)
-            jobs.append(ex.submit(_run, [cc, *FLAGS, "-c", src, "-o", obj]))
+            extra = EXTRA.get(os.path.basename(src), [])
+            jobs.append(ex.submit(_run, [cc, *FLAGS, *extra, "-c", src, "-o", obj]))
         for j in jobs:
             out = j.result()
             if verbose and out.strip():

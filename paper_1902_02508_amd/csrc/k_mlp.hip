@@ -310,6 +310,14 @@ __global__ void __launch_bounds__(256) k_shadows(ClosureView c) {
 
 constexpr int kInferWavesPerCu = 12;
 
+// Two FP32 values to two BF16 (round to nearest even) in one instruction
+// (v_cvt_pk_bf16_f32), packed low | high << 16.
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t bf16x2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{lo, hi}, bf2v));
+}
+
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -320,10 +328,11 @@ __device__ inline void wave_sync() {
 // W2 and W4 in registers for the whole run (W3 is read from LDS) and loops
 // over tiles, fetching the next tile's features while the current one is
 // computed; a tile's activations go through a per-wave 16 x 64 BF16 LDS
-// transpose between layers.
+// transpose between layers. Each layer's products start from its bias (the
+// accumulator's initial value), so the epilogue adds nothing.
 __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__restrict__ feat, long npts,
                                                float *__restrict__ out) {
-  __shared__ float sb[3 * H + 16];
+  __shared__ __attribute__((aligned(16))) float sb[3 * H + 16];
   __shared__ __attribute__((aligned(16))) uint16_t sw3[H * H];
   __shared__ __attribute__((aligned(16))) uint16_t sh[4][16 * H];
   for (int i = threadIdx.x; i < 3 * H + 16; i += 256) {
@@ -373,23 +382,32 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
     const long p = tile * 16 + col;
     const bool pok = p < npts;
     gus8 xb;
+    {
+      float xs[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) xb[e] = e < nf ? g_bf16(fv[e] * fsc[e] + fsh[e]) : (unsigned short)0;
+      for (int e = 0; e < 8; ++e) xs[e] = e < nf ? fv[e] * fsc[e] + fsh[e] : 0.0f;
+      uint32_t w[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) w[e] = bf16x2(xs[2 * e], xs[2 * e + 1]);
+      xb = __builtin_bit_cast(gus8, w);
+    }
     fetch(tile + stride);
+    // the four bias values of accumulator t of a layer whose biases start
+    // at sb + base: rows 16 t + 4 grp .. + 3
+    auto bias = [&](int base, int t) { return *reinterpret_cast<const gf4 *>(sb + base + 16 * t + 4 * grp); };
     gf4 acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = g_mma(a1[t], xb, gf4{0.f, 0.f, 0.f, 0.f});
+    for (int t = 0; t < 4; ++t) acc[t] = g_mma(a1[t], xb, bias(0, t));
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-      // bias and GELU of layer l, transposed through LDS into the next B operand
-      const float *bb = sb + l * H;
+      // GELU of layer l, transposed through LDS into the next B operand
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        uint16_t hv[4];
+        float hv[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) hv[r] = g_bf16(gelu(acc[t][r] + bb[16 * t + 4 * grp + r]));
+        for (int r = 0; r < 4; ++r) hv[r] = gelu(acc[t][r]);
         *reinterpret_cast<uint2 *>(hs + col * H + 16 * t + 4 * grp) =
-            make_uint2(hv[0] | ((uint32_t)hv[1] << 16), hv[2] | ((uint32_t)hv[3] << 16));
+            make_uint2(bf16x2(hv[0], hv[1]), bf16x2(hv[2], hv[3]));
       }
       wave_sync();
       gus8 bk[2];
@@ -399,7 +417,7 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
       if (l < 2) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          acc[t] = gf4{0.f, 0.f, 0.f, 0.f};
+          acc[t] = bias((l + 1) * H, t);
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
             const gus8 aw = l == 0 ? a2[t][s]
@@ -408,13 +426,13 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
           }
         }
       } else {
-        gf4 y = gf4{0.f, 0.f, 0.f, 0.f};
+        gf4 y = bias(3 * H, 0);   // output biases, zero past the sixth row
 #pragma unroll
         for (int s = 0; s < 2; ++s) y = g_mma(a4[s], bk[s], y);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int o = 4 * grp + r;
-          if (o < kMlpOut && pok) out[(long)o * npts + p] = (y[r] + sb[3 * H + o]) * c.isc[o] + c.ish[o];
+          if (o < kMlpOut && pok) out[(long)o * npts + p] = y[r] * c.isc[o] + c.ish[o];
         }
       }
     }
