@@ -349,7 +349,8 @@ struct Lanes {
 struct Ctx {
   __amdgpu_buffer_rsrc_t sa, sb, dst;
   Lanes L;
-  int b, ca, cb;   // MID: field; products: its factors
+  int b, ca, cb;       // MID: field; products: its factors
+  float msh[kDNT];     // products: the shift m(y) of each of the lane's columns
 };
 
 template <bool LAST, bool PROD>
@@ -357,6 +358,8 @@ __device__ __attribute__((always_inline)) inline void make_ctx(const DT &a, long
   const int i = threadIdx.x & 15;
   const int n = a.ax.n;
   c.b = c.ca = c.cb = 0;
+#pragma unroll
+  for (int t = 0; t < kDNT; ++t) c.msh[t] = 0.0f;
   if (LAST) {
     const long r0 = dg * 16 * kDNT;
     const long rows = min((long)16 * kDNT, a.R - r0);
@@ -370,9 +373,10 @@ __device__ __attribute__((always_inline)) inline void make_ctx(const DT &a, long
       c.L.loff[t] = (unsigned)((16 * t + i) * n * 4);
     }
   } else {
-    const long cg = dg / a.nb;
-    c.b = (int)(dg - cg * a.nb);
-    const long c0 = cg * 16 * kDNT;
+    // data-group indices stay below 2^31 (columns / 16 times fields)
+    const int cg = (int)dg / a.nb;
+    c.b = (int)dg - cg * a.nb;
+    const long c0 = (long)cg * 16 * kDNT;
     const size_t bytes = ((size_t)(n - 1) * a.C + (a.C - c0)) * 4;
     if (PROD) {
       dfield(c.b, c.ca, c.cb);
@@ -388,6 +392,10 @@ __device__ __attribute__((always_inline)) inline void make_ctx(const DT &a, long
     for (int t = 0; t < kDNT; ++t) {
       c.L.lv[t] = c0 + 16 * t + i < a.C;
       c.L.loff[t] = (unsigned)((16 * t + i) * 4);
+      // a lane's column (y nz + z) is fixed for the data group, and so is
+      // its y (columns past the data take the last row's shift; their
+      // values are zero and stay zero)
+      if (PROD) c.msh[t] = a.prof[(int)min(c0 + 16 * t + i, (long)a.C - 1) / a.nz];
     }
   }
 }
@@ -461,12 +469,7 @@ __device__ __attribute__((always_inline)) inline void fwd_stream(const DT &a, lo
       const unsigned o0 = live && c.L.lv[t] ? c.L.loff[t] : kOOB;
       G.x0[t] = bload(c.sa, o0);
       G.x0b[t] = PROD ? bload(c.sb, o0) : 0.0f;
-      G.msh[t] = 0.0f;
-      if (PROD) {
-        // shift m(y) of this lane's column (MID: column c = y nz + z)
-        const long col = (long)(c.L.loff[t] / 4) + (long)((kl < nd ? d0 + kl * dstep : d0) / a.nb) * 16 * kDNT;
-        G.msh[t] = a.prof[(int)(min(col, a.C - 1) / a.nz)];
-      }
+      G.msh[t] = c.msh[t];
     }
     if (LAST) {
       // four consecutive nodes k0 .. k0+3 and their partners n-k0-3 .. n-k0
