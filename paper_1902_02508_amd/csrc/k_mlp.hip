@@ -332,9 +332,13 @@ __device__ inline void wave_sync() {
 // accumulator's initial value), so the epilogue adds nothing.
 __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__restrict__ feat, long npts,
                                                float *__restrict__ out) {
+  // LDS rows of W3 and of the activation transposes are HP = H + 8 BF16
+  // (36 words): the sixteen lanes of a lane group, one row each, then fall
+  // on disjoint banks (a 32-word stride puts them all on the same ones)
+  constexpr int HP = H + 8;
   __shared__ __attribute__((aligned(16))) float sb[3 * H + 16];
-  __shared__ __attribute__((aligned(16))) uint16_t sw3[H * H];
-  __shared__ __attribute__((aligned(16))) uint16_t sh[4][16 * H];
+  __shared__ __attribute__((aligned(16))) uint16_t sw3[H * HP];
+  __shared__ __attribute__((aligned(16))) uint16_t sh[4][16 * HP];
   for (int i = threadIdx.x; i < 3 * H + 16; i += 256) {
     float b = 0.0f;
     if (i < H) b = c.theta[kMlpOffB1 + i];
@@ -344,7 +348,8 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
     sb[i] = b;
   }
   for (int i = threadIdx.x; i < H * H / 8; i += 256)
-    reinterpret_cast<gus8 *>(sw3)[i] = reinterpret_cast<const gus8 *>(c.w3)[i];
+    *reinterpret_cast<gus8 *>(sw3 + (i / (H / 8)) * HP + 8 * (i % (H / 8))) =
+        reinterpret_cast<const gus8 *>(c.w3)[i];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, grp = lane >> 4;
@@ -406,13 +411,13 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
         float hv[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) hv[r] = gelu(acc[t][r]);
-        *reinterpret_cast<uint2 *>(hs + col * H + 16 * t + 4 * grp) =
+        *reinterpret_cast<uint2 *>(hs + col * HP + 16 * t + 4 * grp) =
             make_uint2(bf16x2(hv[0], hv[1]), bf16x2(hv[2], hv[3]));
       }
       wave_sync();
       gus8 bk[2];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) bk[s] = *reinterpret_cast<const gus8 *>(hs + col * H + 32 * s + 8 * grp);
+      for (int s = 0; s < 2; ++s) bk[s] = *reinterpret_cast<const gus8 *>(hs + col * HP + 32 * s + 8 * grp);
       wave_sync();
       if (l < 2) {
 #pragma unroll
@@ -421,7 +426,7 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
             const gus8 aw = l == 0 ? a2[t][s]
-                                   : *reinterpret_cast<const gus8 *>(sw3 + (16 * t + col) * H + 32 * s + 8 * grp);
+                                   : *reinterpret_cast<const gus8 *>(sw3 + (16 * t + col) * HP + 32 * s + 8 * grp);
             acc[t] = g_mma(aw, bk[s], acc[t]);
           }
         }
