@@ -269,8 +269,24 @@ def run(n_train=32, n_heldout=4, steps=20000, batch=65536, lr=1e-3, seed=1, work
     return res, cl, f
 
 
+def time_inference(workload: str, reps: int = 20, seed: int = 1):
+    """Exact stress path against the closure's inference on one snapshot of
+    a workload, with random weights (the cost does not depend on their
+    values) and unit feature / output normalisation."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    cfg = synth.config(workload)
+    f = eles.Filter.from_config(cfg, tail_tol=1e-8, device=dev)
+    norms = np.concatenate([np.zeros(10), np.ones(10), np.zeros(6), np.ones(6)])
+    cl = eles.Closure(init_params(seed), norms, device=dev)
+    out = time_paths(cl, f, cfg, dev, reps=reps)
+    out["workload"] = f"{cfg.nx}x{cfg.ny}x{cfg.nz}"
+    return out
+
+
 def main(argv=None):
     p = argparse.ArgumentParser()
+    p.add_argument("--time-inference", metavar="WORKLOAD", default=None,
+                   help="only time the exact path against the closure's inference (random weights) and exit")
     p.add_argument("--train", type=int, default=32)
     p.add_argument("--heldout", type=int, default=4)
     p.add_argument("--steps", type=int, default=20000)
@@ -280,6 +296,9 @@ def main(argv=None):
     p.add_argument("--production", type=int, default=0, metavar="N",
                    help="also time exact path vs closure on N staged 1024x385x768 snapshots")
     a = p.parse_args(argv)
+    if a.time_inference:
+        print(json.dumps(time_inference(a.time_inference)), flush=True)
+        return
     log = lambda m: print(m, file=sys.stderr, flush=True)
     res, cl, f = run(a.train, a.heldout, a.steps, a.batch, a.lr, a.seed, log=log)
     if a.production > 0:
