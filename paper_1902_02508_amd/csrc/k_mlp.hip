@@ -489,12 +489,20 @@ __global__ void __launch_bounds__(256) k_plane_part(const float *f, int nx, int 
   __shared__ double red[256];
   const int j = blockIdx.x, q = blockIdx.y, sp = blockIdx.z;
   const int xb = (int)((long)nx * sp / kPlaneSplit), xe = (int)((long)nx * (sp + 1) / kPlaneSplit);
-  const long cnt = (long)(xe - xb) * nz;
   const float *base = f + (long)q * nx * ny * nz;
   double s = 0.0;
-  for (long t = threadIdx.x; t < cnt; t += 256) {
-    const long x = xb + t / nz, z = t % nz;
-    s += (double)base[(x * ny + j) * nz + z];
+  // element t = (x - xb) nz + z of the slab, walked with 32-bit (x, z)
+  // steps of 256 (no division per element)
+  int x = xb + (int)threadIdx.x / nz, z = (int)threadIdx.x % nz;
+  const int dx = 256 / nz, dz = 256 % nz;
+  while (x < xe) {
+    s += (double)base[((long)x * ny + j) * nz + z];
+    x += dx;
+    z += dz;
+    if (z >= nz) {
+      z -= nz;
+      ++x;
+    }
   }
   red[threadIdx.x] = s;
   __syncthreads();

@@ -191,9 +191,17 @@ __global__ void __launch_bounds__(kT) k_mean(OpsView v, const float *u1) {
   const int sx = v.nx / ns;
   const long cnt = (long)ns * v.nz;
   double part = 0.0;
-  for (long t = threadIdx.x; t < cnt; t += kT) {
-    int q = (int)(t / v.nz), z = (int)(t % v.nz);
+  // element t = q nz + z, walked with 32-bit (q, z) steps of kT
+  int q = (int)threadIdx.x / v.nz, z = (int)threadIdx.x % v.nz;
+  const int dq = kT / v.nz, dz = kT % v.nz;
+  while (q < ns) {
     part += (double)u1[((size_t)(q * sx) * v.ny + j) * v.nz + z];
+    q += dq;
+    z += dz;
+    if (z >= v.nz) {
+      z -= v.nz;
+      ++q;
+    }
   }
   double s = block_sum(part, red);
   if (threadIdx.x == 0) {
