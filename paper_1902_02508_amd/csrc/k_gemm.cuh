@@ -22,6 +22,14 @@ __device__ inline unsigned short g_bf16(float f) {
 }
 __device__ inline float g_f32(unsigned short h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// Two FP32 values to two BF16 (round to nearest even, as g_bf16) in one
+// instruction (v_cvt_pk_bf16_f32), packed low | high << 16.
+typedef float gf2 __attribute__((ext_vector_type(2)));
+typedef __bf16 gbf2 __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t g_bf16x2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(gf2{lo, hi}, gbf2));
+}
+
 __device__ inline gf4 g_mma(gus8 a, gus8 b, gf4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(gbf8, a), __builtin_bit_cast(gbf8, b), c, 0,
                                                  0, 0);
@@ -42,8 +50,13 @@ struct NTArgs {
 
 // AT: 0 = A is BF16 (bits); 1 = A is FP32, rounded to BF16; 2 = A is FP32,
 // split into hi + lo with three products. BLO: use B's lo part (with AT 2).
+// With FP32 A whose rows and K are multiples of 8 floats from a 16-byte
+// aligned base (a8), a lane's eight values of a K chunk are two float4
+// loads; else eight guarded scalar loads.
 template <int AT, int NT, class Epi>
 __device__ inline void nt_gemm_wave(const NTArgs &g, long m0, int n0, int kb, int ke, int z, Epi &epi) {
+  const bool a8 = AT != 0 && g.K % 8 == 0 && g.lda % 8 == 0 && g.a_bstride % 8 == 0 &&
+                  ((uintptr_t)g.a & 15u) == 0;
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, grp = lane >> 4;
   gf4 acc[NT];
@@ -63,14 +76,30 @@ __device__ inline void nt_gemm_wave(const NTArgs &g, long m0, int n0, int kb, in
       for (int e = 0; e < 8; ++e) rowsum += g_f32(ahi[e]);
     } else {
       const float *ap = (const float *)g.a + z * g.a_bstride + (mok ? m : 0) * g.lda;
+      float v[8];
+      if (a8) {
+        const bool ok = mok && ka < g.K;   // all eight or none
+        const gf4 zero4 = gf4{0.f, 0.f, 0.f, 0.f};
+        const gf4 v0 = ok ? *reinterpret_cast<const gf4 *>(ap + ka) : zero4;
+        const gf4 v1 = ok ? *reinterpret_cast<const gf4 *>(ap + ka + 4) : zero4;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = ka + e;
-        const float v = (mok && k < g.K) ? ap[k] : 0.0f;
-        const unsigned short h = g_bf16(v);
-        ahi[e] = h;
-        if (AT == 2) alo[e] = g_bf16(v - g_f32(h));
+        for (int e = 0; e < 4; ++e) {
+          v[e] = v0[e];
+          v[4 + e] = v1[e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (mok && ka + e < g.K) ? ap[ka + e] : 0.0f;
       }
+      uint32_t hw[4], lw[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        hw[e] = g_bf16x2(v[2 * e], v[2 * e + 1]);
+        if (AT == 2)
+          lw[e] = g_bf16x2(v[2 * e] - __uint_as_float(hw[e] << 16), v[2 * e + 1] - __uint_as_float(hw[e] & 0xffff0000u));
+      }
+      ahi = __builtin_bit_cast(gus8, hw);
+      if (AT == 2) alo = __builtin_bit_cast(gus8, lw);
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {

@@ -310,13 +310,6 @@ __global__ void __launch_bounds__(256) k_shadows(ClosureView c) {
 
 constexpr int kInferWavesPerCu = 12;
 
-// Two FP32 values to two BF16 (round to nearest even) in one instruction
-// (v_cvt_pk_bf16_f32), packed low | high << 16.
-typedef float f2v __attribute__((ext_vector_type(2)));
-typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
-__device__ inline uint32_t bf16x2(float lo, float hi) {
-  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{lo, hi}, bf2v));
-}
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -393,7 +386,7 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
       for (int e = 0; e < 8; ++e) xs[e] = e < nf ? fv[e] * fsc[e] + fsh[e] : 0.0f;
       uint32_t w[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) w[e] = bf16x2(xs[2 * e], xs[2 * e + 1]);
+      for (int e = 0; e < 4; ++e) w[e] = g_bf16x2(xs[2 * e], xs[2 * e + 1]);
       xb = __builtin_bit_cast(gus8, w);
     }
     fetch(tile + stride);
@@ -412,7 +405,7 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
 #pragma unroll
         for (int r = 0; r < 4; ++r) hv[r] = gelu(acc[t][r]);
         *reinterpret_cast<uint2 *>(hs + col * HP + 16 * t + 4 * grp) =
-            make_uint2(bf16x2(hv[0], hv[1]), bf16x2(hv[2], hv[3]));
+            make_uint2(g_bf16x2(hv[0], hv[1]), g_bf16x2(hv[2], hv[3]));
       }
       wave_sync();
       gus8 bk[2];
