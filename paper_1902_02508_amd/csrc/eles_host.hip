@@ -808,26 +808,31 @@ int32_t closure_features(eles_filter f, const float *ubar, float *feat, hipStrea
   ya.out_xs = 0;
   ya.out_ks = (size_t)ny * nz;
   if (eles::launch_y(ya, false, ELES_YGEMM_BF16X3, stream) != hipSuccess) return ELES_EHIP;
-  // d/dy: three-point difference with the parities of (u1, u2, u3)
-  eles::YArgs yb = y_args(f);
-  yb.a32[0] = g.dy32[0];
-  yb.a32[1] = g.dy32[1];
-  yb.ahi[0] = g.dyhi[0];
-  yb.ahi[1] = g.dyhi[1];
-  yb.alo[0] = g.dylo[0];
-  yb.alo[1] = g.dylo[1];
-  yb.rowband = g.dyband;
-  yb.nfield = 3;
-  yb.parity_mask = 0x2;
-  yb.in = ubar;
-  yb.in_fs = n;
-  yb.in_xs = (size_t)ny * nz;
-  yb.in_ks = nz;
-  yb.out = feat + n;
-  yb.out_fs = 3 * n;
-  yb.out_xs = (size_t)ny * nz;
-  yb.out_ks = nz;
-  if (eles::launch_y(yb, false, ELES_YGEMM_FP32, stream) != hipSuccess) return ELES_EHIP;
+  // d/dy: three-point difference with the parities of (u1, u2, u3),
+  // streamed along each column (grids of three or more rows)
+  if (ny >= 3) {
+    if (eles::launch_ddy(g, ubar, feat + n, (long)(3 * n), 0x2, stream) != hipSuccess) return ELES_EHIP;
+  } else {
+    eles::YArgs yb = y_args(f);
+    yb.a32[0] = g.dy32[0];
+    yb.a32[1] = g.dy32[1];
+    yb.ahi[0] = g.dyhi[0];
+    yb.ahi[1] = g.dyhi[1];
+    yb.alo[0] = g.dylo[0];
+    yb.alo[1] = g.dylo[1];
+    yb.rowband = g.dyband;
+    yb.nfield = 3;
+    yb.parity_mask = 0x2;
+    yb.in = ubar;
+    yb.in_fs = n;
+    yb.in_xs = (size_t)ny * nz;
+    yb.in_ks = nz;
+    yb.out = feat + n;
+    yb.out_fs = 3 * n;
+    yb.out_xs = (size_t)ny * nz;
+    yb.out_ks = nz;
+    if (eles::launch_y(yb, false, ELES_YGEMM_FP32, stream) != hipSuccess) return ELES_EHIP;
+  }
   // d/dz: rows times the transposed spectral operator
   if (eles::launch_dz(g, ubar, feat + 2 * n, (long)(3 * n), stream) != hipSuccess) return ELES_EHIP;
   if (eles::launch_walldist(f->v.y64, nx, ny, nz, feat + 9 * n, stream) != hipSuccess) return ELES_EHIP;

@@ -153,6 +153,10 @@ struct GradView {
 };
 hipError_t launch_build_grad_ops(const GradView &v, const double *y64, hipStream_t s);
 hipError_t launch_dz(const GradView &v, const float *ubar, float *out, long out_fstride, hipStream_t s);
+// d/dy of the three fields at ubar (parities in pmask, bit f: odd) into
+// out + f * out_fstride; needs ny >= 3
+hipError_t launch_ddy(const GradView &v, const float *ubar, float *out, long out_fstride, unsigned pmask,
+                      hipStream_t s);
 hipError_t launch_walldist(const double *y64, int nx, int ny, int nz, float *out, hipStream_t s);
 
 // ---- the perceptron

@@ -70,6 +70,68 @@ __global__ void __launch_bounds__(256) k_dy(const double *y, int ny, int mp, int
   }
 }
 
+// d/dy of the three filtered velocities, one lane per (field, y segment,
+// x, z) walking its rows with a three-value window: the interior rows of
+// the operator are the central three-point differences (columns j - 1 ..
+// j + 1), the wall rows those of the mirror extension (columns 0, 1 and
+// ny - 2, ny - 1), with the FP32 weights of the operator rows built by
+// k_dy. Rows are requested in chunks of kDyU, the next chunk before the
+// current one is used; kDySeg segments per column keep enough columns in
+// flight.
+constexpr int kDyU = 8;
+constexpr int kDySeg = 4;
+__global__ void __launch_bounds__(64) k_ddy(GradView v, const float *__restrict__ u, float *__restrict__ out,
+                                            long ofs, unsigned pmask) {
+  const int z = blockIdx.x * 64 + threadIdx.x;
+  const int x = blockIdx.y, f = blockIdx.z / kDySeg, sg = blockIdx.z % kDySeg;
+  const int ny = v.ny, nz = v.nz;
+  const int per = (ny + kDySeg - 1) / kDySeg;
+  const int jb = sg * per, je = min(ny, jb + per);   // rows [jb, je) of this segment
+  if (z >= nz || jb >= je) return;
+  const long kp = v.kpy;
+  const float *D = ((pmask >> f) & 1) ? v.dy32[1] : v.dy32[0];
+  const size_t n = (size_t)v.nx * ny * nz;
+  const float *uc = u + f * n + (size_t)x * ny * nz + z;
+  float *oc = out + f * ofs + (size_t)x * ny * nz + z;
+  // window: rows j - 1 and j (row 0 has no j - 1; its weight reads row 0)
+  float um = uc[(size_t)max(jb - 1, 0) * nz], u0 = uc[(size_t)jb * nz];
+  float a[kDyU], b[kDyU];
+  // w[e] = row j0 + e + 1 (clamped), the j + 1 of row j0 + e
+  auto fetch = [&](float (&w)[kDyU], int j0) {
+#pragma unroll
+    for (int e = 0; e < kDyU; ++e) w[e] = uc[(size_t)min(j0 + e + 1, ny - 1) * nz];
+  };
+  auto rows = [&](const float (&w)[kDyU], int j0) {
+#pragma unroll
+    for (int e = 0; e < kDyU; ++e) {
+      const int j = j0 + e;
+      if (j < je) {
+        float o;
+        if (j == 0) {
+          o = D[0] * u0 + D[1] * w[e];
+        } else if (j == ny - 1) {
+          const float *Dl = D + (long)j * kp + (j - 1);
+          o = Dl[0] * um + Dl[1] * u0;
+        } else {
+          const float *Dr = D + (long)j * kp + (j - 1);
+          o = Dr[0] * um + Dr[1] * u0 + Dr[2] * w[e];
+        }
+        oc[(size_t)j * nz] = o;
+        um = u0;
+        u0 = w[e];
+      }
+    }
+  };
+  fetch(a, jb);
+  for (int j0 = jb; j0 < je; j0 += 2 * kDyU) {
+    fetch(b, j0 + kDyU);
+    rows(a, j0);
+    if (j0 + kDyU >= je) break;
+    fetch(a, j0 + 2 * kDyU);
+    rows(b, j0 + kDyU);
+  }
+}
+
 __global__ void __launch_bounds__(256) k_walldist(const double *y, int nx, int ny, int nz, float *out) {
   const long n = (long)nx * ny * nz;
   const long idx = (long)blockIdx.x * 256 + threadIdx.x;
@@ -133,6 +195,14 @@ hipError_t launch_dz(const GradView &v, const float *ubar, float *out, long out_
   const long mtiles = (M + 15) / 16;
   dim3 grid((unsigned)((mtiles + 3) / 4), (unsigned)((v.nz + 63) / 64), 3);
   k_dz<<<grid, 256, 0, s>>>(g, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_ddy(const GradView &v, const float *ubar, float *out, long out_fstride, unsigned pmask,
+                      hipStream_t s) {
+  if (v.ny < 3) return hipErrorInvalidValue;
+  k_ddy<<<dim3((unsigned)((v.nz + 63) / 64), (unsigned)v.nx, 3 * kDySeg), 64, 0, s>>>(v, ubar, out, out_fstride,
+                                                                                   pmask);
   return hipGetLastError();
 }
 
