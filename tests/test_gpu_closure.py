@@ -42,7 +42,11 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("base,over", [("tiny", {}), ("dns192", dict(nx=40, nz=36, ny=33)),
-                                       ("tiny", dict(nx=15, nz=21, ny=17, ykind="tanh", stretch=2.0))])
+                                       ("tiny", dict(nx=15, nz=21, ny=17, ykind="tanh", stretch=2.0)),
+                                       # y segments of 2, 2, 1 rows and of one row (the wall rows
+                                       # alone in theirs); two z blocks, the second partial
+                                       ("tiny", dict(nx=8, nz=70, ny=5)),
+                                       ("tiny", dict(nx=12, nz=8, ny=4))])
 def test_features_match_oracle(E, base, over):
     cfg = synth.config(base, **over)
     y, u = synth.make_snapshot(cfg, 2)
