@@ -19,12 +19,11 @@ checked against.
   uses the mirror node of the extension of eq. (7): the neighbour across the
   wall carries s f(y_1) at the same distance, s being the field's parity.
 * Network: h_l = GELU(W_l h_{l-1} + b_l) for the hidden layers, a linear
-  output layer. GELU(x) = x Phi(x) is evaluated without transcendentals as
-  max(x, 0) - h(min(|x|, 4)), h(s) = sum_k c_k s^k (k = 1..7) a fit of
-  s Phi(-s) with c_1 = 1/2 (the slope of x Phi(x) at 0); it stays within
-  2.4e-4 of x Phi(x) everywhere, below the BF16 resolution of the
-  activations. Inputs and targets are standardised with training-set means
-  and standard deviations.
+  output layer. GELU(x) = x Phi(x) with Phi the standard normal CDF,
+  evaluated through the error function: Phi(x) = (1 + erf(x / sqrt 2)) / 2;
+  its derivative is Phi(x) + x phi(x), phi the normal density. Inputs and
+  targets are standardised with training-set means and standard
+  deviations.
 * Loss: mean over the batch and the six outputs of the squared error.
 * Adam (Kingma & Ba 2015) with bias correction, no weight decay.
 * Minibatch sampler: SplitMix64 (Steele, Lea & Flood 2014), output n of a
@@ -89,41 +88,16 @@ def features(ubar: np.ndarray, y: np.ndarray, lx: float, lz: float) -> np.ndarra
 
 # --------------------------------------------------------------------- MLP
 
-# coefficients c_1..c_7 of h(s), exactly representable in FP32
-GELU_C = (0.5, -0.3894234895706177, -0.04402020201086998, 0.14029717445373535,
-          -0.05751597508788109, 0.009885221719741821, -0.0006385124288499355)
-GELU_CLAMP = 4.0
-
-
-def _h(s):
-    acc = np.zeros_like(s)
-    for c in reversed(GELU_C):
-        acc = (acc + c) * s
-    return acc
-
-
-def _dh(s):
-    acc = np.zeros_like(s)
-    for k in reversed(range(len(GELU_C))):
-        acc = acc * s + (k + 1) * GELU_C[k]
-    return acc
-
-
 def gelu(x):
+    """x Phi(x), Phi(x) = (1 + erf(x / sqrt 2)) / 2."""
     x = np.asarray(x, dtype=np.float64)
-    return np.maximum(x, 0.0) - _h(np.minimum(np.abs(x), GELU_CLAMP))
+    return 0.5 * x * (1.0 + erf(x / math.sqrt(2.0)))
 
 
 def gelu_grad(x):
+    """d/dx x Phi(x) = Phi(x) + x phi(x), phi(x) = exp(-x^2 / 2) / sqrt(2 pi)."""
     x = np.asarray(x, dtype=np.float64)
-    s = np.abs(x)
-    dh = np.where(s < GELU_CLAMP, _dh(np.minimum(s, GELU_CLAMP)), 0.0)
-    return np.where(x >= 0.0, 1.0 - dh, dh)
-
-
-def gelu_erf(x):
-    """x Phi(x) with the exact normal CDF (what gelu approximates)."""
-    return 0.5 * x * (1.0 + erf(np.asarray(x, dtype=np.float64) / math.sqrt(2.0)))
+    return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
 
 
 def param_shapes(layers: Sequence[int] = LAYERS) -> List[Tuple[int, ...]]:

@@ -65,26 +65,43 @@ def test_features_of_an_analytic_field():
 
 
 def test_gelu_special_values():
+    """x Phi(x): zero at 0 with slope 1/2; gelu(x) - gelu(-x) = x (Phi(-x) =
+    1 - Phi(x)); tabulated normal-CDF values; the identity and zero limits."""
     assert C.gelu(0.0) == 0.0
     assert abs(C.gelu_grad(0.0) - 0.5) < 1e-15
-    assert abs(C.gelu(10.0) - 10.0) < 3e-4 and abs(C.gelu(-10.0)) < 3e-4
-    # every coefficient is an FP32 number
-    assert all(float(np.float32(c)) == c for c in C.GELU_C)
-    x = np.concatenate([np.linspace(-5, 5, 101), [-4.0 + 1e-3, 4.0 - 1e-3]])
-    x = x[np.abs(np.abs(x) - 4.0) > 1e-5]
+    # Phi(1) and Phi(1.96) from standard normal tables (Abramowitz & Stegun 26.2)
+    assert abs(C.gelu(1.0) - 0.8413447460685429) < 1e-15
+    assert abs(C.gelu(-1.96) + 1.96 * (1.0 - 0.9750021048517795)) < 1e-15
+    x = np.linspace(-8, 8, 161)
+    assert np.max(np.abs(C.gelu(x) - C.gelu(-x) - x)) < 1e-14
+    assert abs(C.gelu(40.0) - 40.0) < 1e-12 and abs(C.gelu(-40.0)) < 1e-300
     h = 1e-6
     fd = (C.gelu(x + h) - C.gelu(x - h)) / (2 * h)
     assert np.max(np.abs(fd - C.gelu_grad(x))) < 1e-8
 
 
-def test_gelu_is_close_to_the_normal_cdf_form():
-    """max |gelu(x) - x Phi(x)| over the whole line, Phi from the error function."""
+def test_gelu_is_x_times_the_integrated_normal_density():
+    """Phi by quadrature of the normal density, independent of erf."""
+    from scipy.integrate import quad
+    dens = lambda t: math.exp(-0.5 * t * t) / math.sqrt(2 * math.pi)  # noqa: E731
+    for x in (-5.5, -2.3, -0.4, 0.25, 1.7, 3.9):
+        half, _ = quad(dens, 0.0, x, epsabs=1e-15, epsrel=1e-13)
+        phi = 0.5 + half
+        assert abs(C.gelu(x) - x * phi) < 1e-13, x
+        assert abs(C.gelu_grad(x) - (phi + x * dens(x))) < 1e-13, x
+
+
+def test_kernel_gelu_approximation_bound():
+    """The GPU kernels approximate x Phi(x) by max(x, 0) - h(min(|x|, 4)) with
+    h a degree-7 polynomial; this bounds that approximation against the
+    definition: 2.4e-4 on the value, 5e-3 on the derivative (its worst point
+    is the clamp at |x| = 4). The GPU parity tolerances carry its effect."""
+    import kernel_gelu as K
+    assert all(float(np.float32(v)) == v for v in K.coefficients())
+    assert K.coefficients()[0] == 0.5          # slope 1/2 at 0, as x Phi(x)
     x = np.linspace(-30, 30, 600001)
-    assert np.max(np.abs(C.gelu(x) - C.gelu_erf(x))) < 2.4e-4
-    # the derivative follows Phi(x) + x phi(x) to 5e-3 (its worst point is the
-    # clamp at |x| = 4); the backward pass stores it in BF16 (resolution 2^-8)
-    d = 0.5 * (1 + C.erf(x / math.sqrt(2))) + x * np.exp(-0.5 * x * x) / math.sqrt(2 * math.pi)
-    assert np.max(np.abs(C.gelu_grad(x) - d)) < 5e-3
+    assert np.max(np.abs(K.gelu(x) - C.gelu(x))) < 2.4e-4
+    assert np.max(np.abs(K.gelu_grad(x) - C.gelu_grad(x))) < 5e-3
 
 
 def test_backprop_matches_finite_differences():

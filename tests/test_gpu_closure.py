@@ -4,6 +4,7 @@ import math
 import numpy as np
 import pytest
 
+import kernel_gelu
 from oracle import closure_ref as C
 from oracle import filter_ref as R
 from paper_1902_02508_amd import synth
@@ -92,6 +93,11 @@ def _emulated_forward(theta, xs):
 
 
 def test_inference_matches_oracle(E):
+    """The network against the FP64 reference with the exact GELU. Tolerance:
+    the BF16 roundings (2e-3 against a BF16 emulation of the reference, 3e-2
+    against FP64) plus the effect of the kernels' GELU fit on these inputs,
+    the FP64 network with the fit against the same network with x Phi(x)
+    (the fit itself is bounded by 2.4e-4 on the CPU)."""
     cfg = synth.config("dns192", nx=32, nz=32, ny=33)
     y, u = synth.make_snapshot(cfg, 4)
     f = E.Filter.from_config(cfg)
@@ -104,13 +110,16 @@ def test_inference_matches_oracle(E):
     pred, st = cl.infer(f, ub)
     pred = _host(pred)
     xs = ((feat.reshape(10, -1).T - norms[:10]) / norms[10:20])
-    ref_std = C.forward(theta.astype(np.float32).astype(np.float64), xs)
+    th32 = theta.astype(np.float32).astype(np.float64)
+    ref_std = C.forward(th32, xs)
     ref = ref_std * norms[26:32] + norms[20:26]
     emu = _emulated_forward(theta, xs) * norms[26:32] + norms[20:26]
+    fit_rel = _rel(kernel_gelu.forward(C.unpack, th32, xs) * norms[26:32], ref_std * norms[26:32])
     got = pred.reshape(6, -1).T
     e_exact, e_emu = _rel(got, ref), _rel(got, emu)
-    print(f"inference rel error vs FP64 {e_exact:.2e}, vs BF16 emulation {e_emu:.2e}", flush=True)
-    assert e_emu < 2e-3 and e_exact < 3e-2
+    print(f"inference rel error vs FP64 {e_exact:.2e}, vs BF16 emulation {e_emu:.2e}; "
+          f"effect of the GELU fit {fit_rel:.2e}", flush=True)
+    assert e_emu < 2e-3 + fit_rel and e_exact < 3e-2 + fit_rel
     assert np.allclose(_host(st), pred.mean(axis=(1, 3)), rtol=1e-10, atol=1e-14)
 
 
@@ -129,7 +138,9 @@ def _dataset(E, n_snap=2):
 
 def test_gradient_matches_oracle(E):
     """One Adam step with beta1 = beta2 = 0 and a large eps moves every weight
-    by -lr g / (|g| + eps), which is inverted for the gradient g."""
+    by -lr g / (|g| + eps), which is inverted for the gradient g. Tolerance
+    2e-2: BF16 storage of activations and of GELU' (2^-8 each) plus the
+    kernels' GELU-derivative fit (within 5e-3 of Phi(x) + x phi(x))."""
     cfg, feat, tau = _dataset(E)
     fh, th = _host(feat), _host(tau)
     norms = _norms(np.moveaxis(fh, 1, 0), np.moveaxis(th, 1, 0))
