@@ -34,15 +34,16 @@
  * *_destroy frees host memory only.
  *
  * Execution. Every call enqueues work on the given stream and returns
- * without waiting for it, except filter_setup, which copies the host y
- * array to the device, builds the operators and waits for the stream (it
- * reads the operators' band structure back to plan the y pass). One handle
- * must not be used from two streams or threads at once. All device
- * pointers must be 16-byte aligned.
+ * without waiting for it, except the ones that read device results on the
+ * host, which wait for their stream: the setup calls (filter_setup reads
+ * the operators' band structure back to plan the y pass), closure_create,
+ * closure_get_params / closure_set_params, and closure_infer in its
+ * checked modes. One handle must not be used from two streams or threads
+ * at once. All device pointers must be 16-byte aligned.
  *
  * Errors. Arguments are validated before anything is enqueued; a failing
- * call returns a non-zero eles_status and enqueues nothing. A HIP error
- * at launch returns ELES_EHIP. No exception crosses the ABI.
+ * validation returns a non-zero eles_status and enqueues nothing. A HIP
+ * error at launch returns ELES_EHIP. No exception crosses the ABI.
  */
 #ifndef ELES_H
 #define ELES_H
@@ -335,7 +336,11 @@ void les_destroy(eles_les h);
  * The paper proposes using the exact stress computed from DNS data to
  * inform subgrid models, naming machine learning as one route (Sec. 2.1,
  * last paragraph; Sec. 5). This closure is a perceptron 10 -> 64 -> 64 ->
- * 64 -> 6 with GELU (x Phi(x)) hidden layers and a linear output. Its
+ * 64 -> 6 with GELU hidden layers and a linear output. GELU(x) = x Phi(x),
+ * Phi the standard normal CDF; the kernels evaluate it as max(x, 0) -
+ * h(min(|x|, 4)) with h a degree-7 polynomial fitted to s Phi(-s), within
+ * 2.4e-4 of x Phi(x) (derivative within 5e-3), below the BF16 resolution
+ * of the activations. Its
  * inputs at every grid point are the nine components d ubar_i / d x_k
  * (i, k = 1..3, row-major) of the filtered velocity gradient and the wall
  * distance 1 - |y|; its outputs are tau_11, tau_12, tau_13, tau_22, tau_23,
@@ -371,10 +376,16 @@ int32_t closure_create(void *state, size_t state_bytes, const float *params, con
 /* Adam steps taken so far (-1 for a null handle). */
 int64_t closure_step(eles_closure c);
 
-/* Checkpoint blob: FP32 weights, Adam m and v, FP64 norms, int64 step. */
+/* Checkpoint blob: FP32 weights, Adam m and v, FP64 norms, int64 step.
+ * closure_get_params copies the state into the host blob on the stream
+ * (after the work already queued there) and waits for the stream.
+ * closure_set_params validates the blob on the host (ENUMERIC: non-finite
+ * values or non-positive deviations; EINVAL: negative step), then copies
+ * it on the stream and waits for the stream. Errors: EINVAL (null handle
+ * or blob, bytes < closure_blob_bytes()), ENUMERIC, EHIP. */
 size_t closure_blob_bytes(void);
-int32_t closure_get_params(eles_closure c, void *blob, size_t bytes);  /* waits for the device */
-int32_t closure_set_params(eles_closure c, const void *blob, size_t bytes);
+int32_t closure_get_params(eles_closure c, void *blob, size_t bytes, hipStream_t stream);
+int32_t closure_set_params(eles_closure c, const void *blob, size_t bytes, hipStream_t stream);
 
 /* Features of a filtered velocity ubar (device [3][nx][ny][nz]) on the
  * filter's grid: feat (device [10][nx][ny][nz]) = d ubar_i/dx (spectral,
@@ -389,6 +400,7 @@ size_t closure_moments_workspace_bytes(int32_t nchan);
 int32_t closure_moments(const float *data, int32_t nchan, int32_t nsnap, int64_t npts, double *out, void *ws,
                         size_t ws_bytes, hipStream_t stream);
 
+
 /* Adam training on minibatches drawn from nsnap snapshots of features
  * (device [nsnap][10][npts]) and exact stresses (device [nsnap][6][npts]);
  * loss = mean squared error of the standardised outputs. loss_hist:
@@ -398,12 +410,37 @@ size_t closure_train_workspace_bytes(int32_t batch);
 int32_t closure_train(eles_closure c, const float *feat, const float *tau, int32_t nsnap, int64_t npts,
                       const eles_train_desc *d, float *loss_hist, void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* Predicted stress from a filtered velocity: features, then the network.
- * tau_pred: device [6][nx][ny][nz]; stats: device FP64 [6][ny] plane
- * averages of tau_pred, or NULL. Errors: EINVAL, ENOSPACE, EHIP. */
-size_t closure_infer_workspace_bytes(eles_filter f);
-int32_t closure_infer(eles_closure c, eles_filter f, const float *ubar, float *tau_pred, double *stats, void *ws,
-                      size_t ws_bytes, hipStream_t stream);
+/* Predicted stress from a filtered velocity: features, then the network,
+ * with the exact filtered stress of Sec. 2.1 as the fallback. tau_pred:
+ * device [6][nx][ny][nz]; stats: device FP64 [6][ny] plane averages of
+ * tau_pred (the returned one, network or exact), or NULL.
+ *
+ * fallback selects what happens to a non-finite prediction (a NaN or an
+ * infinity anywhere in tau_pred, detected through the FP64 plane sums of
+ * tau_pred, which carry any of them):
+ *   ELES_INFER_UNCHECKED: no test; the call only enqueues work.
+ *   ELES_INFER_CHECK:     the call waits for the stream and returns
+ *                         ENUMERIC, tau_pred holding the network's output.
+ *   ELES_INFER_FALLBACK:  the call waits for the stream and, on a
+ *                         non-finite prediction, computes the exact stress
+ *                         of u_or_null (device [3][nx][ny][nz], the
+ *                         unfiltered velocity ubar was filtered from) into
+ *                         tau_pred with sgs_stress on the same handle and
+ *                         stream, bit for bit what sgs_stress returns.
+ * *fell_back (host, may be NULL) is set to 1 when the exact stress
+ * replaced the prediction, else 0. u_or_null is read only on fallback and
+ * must not overlap tau_pred or ws. Workspace:
+ * closure_infer_workspace_bytes(f, fallback == ELES_INFER_FALLBACK).
+ * Errors: EINVAL (also fallback out of range, or ELES_INFER_FALLBACK with
+ * u_or_null NULL or misaligned), ENOSPACE, ENUMERIC (ELES_INFER_CHECK
+ * only), EHIP; on fallback, the errors of sgs_stress. */
+#define ELES_INFER_UNCHECKED (-1)
+#define ELES_INFER_CHECK 0
+#define ELES_INFER_FALLBACK 1
+size_t closure_infer_workspace_bytes(eles_filter f, int32_t with_fallback);
+int32_t closure_infer(eles_closure c, eles_filter f, const float *ubar, float *tau_pred, double *stats,
+                      int32_t fallback, const float *u_or_null, int32_t *fell_back, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
 
 /* The minibatch indices the trainer draws at `step` (device int64 [batch]). */
 int32_t closure_sample_indices(uint64_t seed, int64_t step, int32_t batch, uint64_t count, int64_t *out,

@@ -676,6 +676,27 @@ size_t train_ws(int batch, eles::TrainWs *w, char *base) {
   return o;
 }
 
+// Workspace of closure_infer: the features (or, for the exact fallback,
+// the filtered velocity and sgs_stress's workspace), the plane partials,
+// plane sums for the check when the caller passes no stats, the flag.
+struct InferWs {
+  size_t off_sgs, off_part, off_stats, off_flag;
+};
+
+size_t infer_ws(const eles_filter_s *f, bool exact, InferWs *w) {
+  const size_t n = f->npts;
+  size_t r0 = up256(10 * n * 4);
+  const size_t off_sgs = up256(3 * n * 4);
+  if (exact) r0 = std::max(r0, off_sgs + sgs_ws(f, nullptr));
+  InferWs o;
+  o.off_sgs = off_sgs;
+  o.off_part = r0;
+  o.off_stats = o.off_part + up256((size_t)eles::plane_mean_parts(6, f->d.ny) * 8);
+  o.off_flag = o.off_stats + up256((size_t)6 * f->d.ny * 8);
+  if (w) *w = o;
+  return o.off_flag + 256;
+}
+
 }  // namespace
 
 extern "C" {
@@ -737,21 +758,24 @@ int64_t closure_step(eles_closure c) { return c ? c->step : -1; }
 
 size_t closure_blob_bytes(void) { return (size_t)3 * eles::kMlpNParam * 4 + kNorm * 8 + 8; }
 
-int32_t closure_get_params(eles_closure c, void *blob, size_t bytes) {
+int32_t closure_get_params(eles_closure c, void *blob, size_t bytes, hipStream_t stream) {
   if (!c || !blob || bytes < closure_blob_bytes()) return ELES_EINVAL;
   const size_t pb = (size_t)eles::kMlpNParam * 4;
   char *b = (char *)blob;
-  if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(b, c->c.theta, pb, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(b + pb, c->c.m, pb, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(b + 2 * pb, c->c.v, pb, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(b + 3 * pb, c->norm64, kNorm * 8, hipMemcpyDeviceToHost) != hipSuccess)
+  // stream-ordered copies; the host reads the blob, so the call waits for
+  // the stream
+  if (hipMemcpyAsync(b, c->c.theta, pb, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(b + pb, c->c.m, pb, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(b + 2 * pb, c->c.v, pb, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(b + 3 * pb, c->norm64, kNorm * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
     return ELES_EHIP;
   int64_t st = c->step;
   std::memcpy(b + 3 * pb + kNorm * 8, &st, 8);
   return ELES_OK;
 }
 
-int32_t closure_set_params(eles_closure c, const void *blob, size_t bytes) {
+int32_t closure_set_params(eles_closure c, const void *blob, size_t bytes, hipStream_t stream) {
   if (!c || !blob || bytes < closure_blob_bytes()) return ELES_EINVAL;
   const size_t pb = (size_t)eles::kMlpNParam * 4;
   const char *b = (const char *)blob;
@@ -765,12 +789,15 @@ int32_t closure_set_params(eles_closure c, const void *blob, size_t bytes) {
   if (st < 0) return ELES_EINVAL;
   float nrm[kNrm32];
   derive_nrm32(n, nrm);
-  if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(c->c.theta, b, pb, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->c.m, b + pb, pb, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->c.v, b + 2 * pb, pb, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->norm64, n, kNorm * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy((void *)c->c.fsc, nrm, sizeof(nrm), hipMemcpyHostToDevice) != hipSuccess ||
-      eles::launch_shadows(c->c, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+  // stream-ordered after the work already queued on the handle; the call
+  // waits for the stream because the copies read host memory the caller
+  // (and this frame, for nrm) may release on return
+  if (hipMemcpyAsync(c->c.theta, b, pb, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(c->c.m, b + pb, pb, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(c->c.v, b + 2 * pb, pb, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(c->norm64, n, kNorm * 8, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync((void *)c->c.fsc, nrm, sizeof(nrm), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      eles::launch_shadows(c->c, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
     return ELES_EHIP;
   c->step = st;
   return ELES_OK;
@@ -886,26 +913,59 @@ int32_t closure_train(eles_closure c, const float *feat, const float *tau, int32
   return ELES_OK;
 }
 
-size_t closure_infer_workspace_bytes(eles_filter f) {
-  return f ? up256(10 * f->npts * 4) + up256((size_t)eles::plane_mean_parts(6, f->d.ny) * 8) : 0;
+size_t closure_infer_workspace_bytes(eles_filter f, int32_t with_fallback) {
+  return f ? infer_ws(f, with_fallback != 0, nullptr) : 0;
 }
 
-int32_t closure_infer(eles_closure c, eles_filter f, const float *ubar, float *tau_pred, double *stats, void *ws,
-                      size_t ws_bytes, hipStream_t stream) {
-  if (!c || !f || !ubar || !tau_pred || !ws || !aligned16(tau_pred) || !aligned16(ws)) return ELES_EINVAL;
-  if (ws_bytes < closure_infer_workspace_bytes(f)) return ELES_ENOSPACE;
-  const size_t n = f->npts;
-  if (overlap(ubar, 3 * n * 4, tau_pred, 6 * n * 4) || overlap(ws, ws_bytes, tau_pred, 6 * n * 4) ||
-      overlap(ws, ws_bytes, ubar, 3 * n * 4))
+int32_t closure_infer(eles_closure c, eles_filter f, const float *ubar, float *tau_pred, double *stats,
+                      int32_t fallback, const float *u_or_null, int32_t *fell_back, void *ws, size_t ws_bytes,
+                      hipStream_t stream) {
+  if (fell_back) *fell_back = 0;
+  if (!c || !f || !ubar || !tau_pred || !ws || !aligned16(tau_pred) || !aligned16(ws) ||
+      (stats && !aligned16(stats)))
     return ELES_EINVAL;
-  float *feat = (float *)ws;
+  if (fallback < ELES_INFER_UNCHECKED || fallback > ELES_INFER_FALLBACK) return ELES_EINVAL;
+  const bool checked = fallback != ELES_INFER_UNCHECKED, exact = fallback == ELES_INFER_FALLBACK;
+  if (exact && (!u_or_null || !aligned16(u_or_null))) return ELES_EINVAL;
+  InferWs w;
+  const size_t need = infer_ws(f, exact, &w);
+  if (ws_bytes < need) return ELES_ENOSPACE;
+  const size_t n = f->npts, sb = (size_t)6 * f->d.ny * sizeof(double);
+  if (overlap(ubar, 3 * n * 4, tau_pred, 6 * n * 4) || overlap(ws, need, tau_pred, 6 * n * 4) ||
+      overlap(ws, need, ubar, 3 * n * 4) || (stats && (overlap(stats, sb, ws, need) ||
+                                                       overlap(stats, sb, tau_pred, 6 * n * 4))))
+    return ELES_EINVAL;
+  if (exact && (overlap(u_or_null, 3 * n * 4, tau_pred, 6 * n * 4) || overlap(u_or_null, 3 * n * 4, ws, need)))
+    return ELES_EINVAL;
+  char *base = (char *)ws;
+  float *feat = (float *)base;
+  double *part = (double *)(base + w.off_part);
   int32_t st = closure_features(f, ubar, feat, stream);
   if (st != ELES_OK) return st;
   if (eles::launch_infer(c->c, feat, (long)n, tau_pred, stream) != hipSuccess) return ELES_EHIP;
-  double *part = (double *)((char *)ws + up256(10 * n * 4));
-  if (stats &&
-      eles::launch_plane_mean(tau_pred, 6, f->d.nx, f->d.ny, f->d.nz, part, stats, stream) != hipSuccess)
+  // plane sums: the caller's stats, or (for the check alone) the workspace's
+  double *sums = stats ? stats : (checked ? (double *)(base + w.off_stats) : nullptr);
+  if (sums && eles::launch_plane_mean(tau_pred, 6, f->d.nx, f->d.ny, f->d.nz, part, sums, stream) != hipSuccess)
     return ELES_EHIP;
+  if (!checked) return ELES_OK;
+  // a NaN or infinity anywhere in tau_pred makes its plane's FP64 sum
+  // non-finite; the host reads the device flag back
+  int32_t bad = 0;
+  int *flag = (int *)(base + w.off_flag);
+  if (eles::launch_nonfinite(sums, 6 * f->d.ny, flag, stream) != hipSuccess ||
+      hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return ELES_EHIP;
+  if (!bad) return ELES_OK;
+  if (!exact) return ELES_ENUMERIC;
+  // the exact stress replaces the prediction: sgs_stress into tau_pred, its
+  // filtered velocity and workspace in the (now free) feature region
+  float *ub_exact = (float *)base;
+  st = sgs_stress(f, u_or_null, ub_exact, tau_pred, nullptr, base + w.off_sgs, sgs_ws(f, nullptr), stream);
+  if (st != ELES_OK) return st;
+  if (stats && eles::launch_plane_mean(tau_pred, 6, f->d.nx, f->d.ny, f->d.nz, part, stats, stream) != hipSuccess)
+    return ELES_EHIP;
+  if (fell_back) *fell_back = 1;
   return ELES_OK;
 }
 

@@ -201,10 +201,13 @@ hipError_t launch_shadows(const ClosureView &c, hipStream_t s);
 hipError_t launch_infer(const ClosureView &c, const float *feat, long npts, float *out, hipStream_t s);
 hipError_t launch_moments(const float *data, int nchan, int nsnap, long npts, double *part, int nchunks,
                           double *out, hipStream_t s);
-// part: FP64 scratch of plane_mean_parts(nq, ny) values
+// Plane means and the non-finite test (k_check.hip, built with IEEE
+// semantics). part: FP64 scratch of plane_mean_parts(nq, ny) values.
 inline long plane_mean_parts(int nq, int ny) { return (long)nq * ny * 16; }
 hipError_t launch_plane_mean(const float *f, int nq, int nx, int ny, int nz, double *part, double *out,
                              hipStream_t s);
+// *flag (device) = 1 if any of v[0..n) (device FP64) is NaN or infinite.
+hipError_t launch_nonfinite(const double *v, int n, int *flag, hipStream_t s);
 hipError_t launch_train_step(const ClosureView &c, const TrainData &d, const TrainWs &w, uint64_t seed, long step,
                              int batch, AdamArgs adam, hipStream_t s);
 

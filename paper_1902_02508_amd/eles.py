@@ -107,15 +107,15 @@ _SIG = {
     "closure_create": (_I, [_P, _S, _P, _P, _P, ctypes.POINTER(_P)]),
     "closure_step": (ctypes.c_int64, [_P]),
     "closure_blob_bytes": (_S, []),
-    "closure_get_params": (_I, [_P, _P, _S]),
-    "closure_set_params": (_I, [_P, _P, _S]),
+    "closure_get_params": (_I, [_P, _P, _S, _P]),
+    "closure_set_params": (_I, [_P, _P, _S, _P]),
     "closure_features": (_I, [_P, _P, _P, _P]),
     "closure_moments_workspace_bytes": (_S, [_I]),
     "closure_moments": (_I, [_P, _I, _I, ctypes.c_int64, _P, _P, _S, _P]),
     "closure_train_workspace_bytes": (_S, [_I]),
     "closure_train": (_I, [_P, _P, _P, _I, ctypes.c_int64, _P, _P, _P, _S, _P]),
-    "closure_infer_workspace_bytes": (_S, [_P]),
-    "closure_infer": (_I, [_P, _P, _P, _P, _P, _P, _S, _P]),
+    "closure_infer_workspace_bytes": (_S, [_P, _I]),
+    "closure_infer": (_I, [_P, _P, _P, _P, _P, _I, _P, ctypes.POINTER(_I), _P, _S, _P]),
     "closure_sample_indices": (_I, [ctypes.c_uint64, ctypes.c_int64, _I, ctypes.c_uint64, _P, _P]),
     "closure_destroy": (None, [_P]),
 }
@@ -389,16 +389,16 @@ def closure_blob_bytes() -> int:
     return lib.closure_blob_bytes()
 
 
-def closure_get_params(h) -> bytes:
+def closure_get_params(h, stream) -> bytes:
     n = lib.closure_blob_bytes()
     buf = ctypes.create_string_buffer(n)
-    _check(lib.closure_get_params(h, buf, n), "closure_get_params")
+    _check(lib.closure_get_params(h, buf, n, stream), "closure_get_params")
     return buf.raw
 
 
-def closure_set_params(h, blob: bytes):
+def closure_set_params(h, blob: bytes, stream):
     buf = ctypes.create_string_buffer(blob, len(blob))
-    _check(lib.closure_set_params(h, buf, len(blob)), "closure_set_params")
+    _check(lib.closure_set_params(h, buf, len(blob), stream), "closure_set_params")
 
 
 def closure_features(fh, ubar_ptr, feat_ptr, stream):
@@ -422,12 +422,19 @@ def closure_train(h, feat_ptr, tau_ptr, nsnap, npts, desc, loss_ptr, ws_ptr, ws_
                              stream), "closure_train")
 
 
-def closure_infer_workspace_bytes(fh) -> int:
-    return lib.closure_infer_workspace_bytes(fh)
+INFER_UNCHECKED, INFER_CHECK, INFER_FALLBACK = -1, 0, 1
 
 
-def closure_infer(h, fh, ubar_ptr, tau_ptr, stats_ptr, ws_ptr, ws_bytes, stream):
-    _check(lib.closure_infer(h, fh, ubar_ptr, tau_ptr, stats_ptr, ws_ptr, ws_bytes, stream), "closure_infer")
+def closure_infer_workspace_bytes(fh, with_fallback: int = 0) -> int:
+    return lib.closure_infer_workspace_bytes(fh, with_fallback)
+
+
+def closure_infer(h, fh, ubar_ptr, tau_ptr, stats_ptr, fallback, u_ptr, ws_ptr, ws_bytes, stream) -> int:
+    """Returns 1 when the exact stress replaced a non-finite prediction."""
+    fell = _I(0)
+    _check(lib.closure_infer(h, fh, ubar_ptr, tau_ptr, stats_ptr, fallback, u_ptr, ctypes.byref(fell), ws_ptr,
+                             ws_bytes, stream), "closure_infer")
+    return fell.value
 
 
 def closure_sample_indices(seed, step, batch, count, out_ptr, stream):
@@ -495,10 +502,10 @@ class Closure:
         return closure_step(self.h)
 
     def get_params(self) -> bytes:
-        return closure_get_params(self.h)
+        return closure_get_params(self.h, _stream())
 
     def set_params(self, blob: bytes):
-        closure_set_params(self.h, blob)
+        closure_set_params(self.h, blob, _stream())
 
     def theta(self) -> np.ndarray:
         return np.frombuffer(self.get_params(), dtype=np.float32, count=NPARAM).copy()
@@ -522,15 +529,23 @@ class Closure:
                       _ptr(ws), ws.numel(), _stream())
         return loss_hist
 
-    def infer(self, f: "Filter", ubar: torch.Tensor, tau: Optional[torch.Tensor] = None, stats=True):
+    def infer(self, f: "Filter", ubar: torch.Tensor, tau: Optional[torch.Tensor] = None, stats=True,
+              fallback: int = INFER_UNCHECKED, u: Optional[torch.Tensor] = None):
+        """tau_pred [6][...] and its plane means [6][ny] (or None). With
+        fallback=INFER_FALLBACK and the unfiltered velocity u, a non-finite
+        prediction is replaced by the exact stress; self.fell_back reports
+        it. INFER_CHECK raises ElesError (ENUMERIC) instead."""
         f._field_check(ubar, 3)
+        if u is not None:
+            f._field_check(u, 3)
         if tau is None:
             tau = torch.empty((6,) + f.shape, dtype=torch.float32, device=f.device)
         st = torch.empty((6, f.shape[1]), dtype=torch.float64, device=f.device) if stats is True else stats
-        nb = closure_infer_workspace_bytes(f.h)
+        nb = closure_infer_workspace_bytes(f.h, int(fallback == INFER_FALLBACK))
         ws = self._workspace(nb)
-        closure_infer(self.h, f.h, _ptr(ubar), _ptr(tau), _ptr(st) if st is not None else None,
-                      _ptr(ws), ws.numel(), _stream())
+        self.fell_back = closure_infer(self.h, f.h, _ptr(ubar), _ptr(tau), _ptr(st) if st is not None else None,
+                                       fallback, _ptr(u) if u is not None else None, _ptr(ws), ws.numel(),
+                                       _stream())
         return tau, st
 
 

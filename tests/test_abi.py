@@ -123,7 +123,15 @@ def test_closure_validation_without_device(eles):
     assert eles.closure_train_workspace_bytes(0) == 0
     assert eles.closure_train_workspace_bytes(65536) > 65536 * 64
     assert eles.lib.closure_sample_indices(1, 0, 0, 10, 0x1000, None) == eles.ELES_EINVAL
-    assert eles.lib.closure_infer(None, None, 16, 16, None, 16, 1 << 20, None) == eles.ELES_EINVAL
+    fell = C.c_int32(7)
+    for mode in (eles.INFER_UNCHECKED, eles.INFER_CHECK, eles.INFER_FALLBACK, 2, -2):
+        assert eles.lib.closure_infer(None, None, 16, 16, None, mode, 16, C.byref(fell), 16, 1 << 20,
+                                      None) == eles.ELES_EINVAL
+        assert fell.value == 0
+    assert eles.closure_infer_workspace_bytes(None, 1) == 0
+    blob = C.create_string_buffer(eles.closure_blob_bytes())
+    assert eles.lib.closure_get_params(None, blob, len(blob), None) == eles.ELES_EINVAL
+    assert eles.lib.closure_set_params(None, blob, len(blob), None) == eles.ELES_EINVAL
     assert eles.lib.closure_step(None) == -1
     assert eles.closure_blob_bytes() == 3 * 9414 * 4 + 32 * 8 + 8
 

@@ -197,3 +197,63 @@ def test_checkpoint_resume_is_bit_identical(E):
     assert b.step == 12
     b.train(feat, tau, steps=7, batch=256, seed=9)
     assert a.get_params() == b.get_params()
+
+
+def _overflowing_params():
+    """Finite weights whose output layer overflows FP32: the last hidden
+    layer is pushed positive (b3 = 10) and every output weight and bias is
+    3e38, so each output sums positive terms past the FP32 range."""
+    theta = C.init_params(21)
+    p = C.unpack(theta)          # views into theta
+    p[5][:] = 10.0
+    p[6][:] = 3.0e38
+    p[7][:] = 3.0e38
+    return theta
+
+
+def test_infer_falls_back_to_the_exact_stress(E):
+    """A non-finite prediction is replaced by the exact stress of Sec. 2.1,
+    bit for bit what sgs_stress returns; the check alone reports ENUMERIC;
+    a finite prediction passes through every mode unchanged."""
+    import torch
+    cfg = synth.config("dns192", nx=32, nz=40, ny=33)
+    y, u = synth.make_snapshot(cfg, 7)
+    f = E.Filter.from_config(cfg)
+    du = _dev(u)
+    ub, tau, st = f.sgs_stress(du)
+    exact = tau.clone()
+    feat = _host(E.features(f, ub))
+    norms = _norms(feat, _host(tau))
+    bad = E.Closure(_overflowing_params(), norms)
+    pred, pst = bad.infer(f, ub, fallback=E.INFER_UNCHECKED)
+    assert bad.fell_back == 0
+    assert not torch.isfinite(pred).all().item()
+    with pytest.raises(E.ElesError) as ei:
+        bad.infer(f, ub, fallback=E.INFER_CHECK)
+    assert ei.value.status == E.ELES_ENUMERIC
+    pred, pst = bad.infer(f, ub, fallback=E.INFER_FALLBACK, u=du)
+    assert bad.fell_back == 1
+    assert torch.equal(pred, exact)
+    assert np.allclose(_host(pst), _host(pred).mean(axis=(1, 3)), rtol=1e-10, atol=1e-14)
+    with pytest.raises(E.ElesError) as ei:
+        bad.infer(f, ub, fallback=E.INFER_FALLBACK, u=None)
+    assert ei.value.status == E.ELES_EINVAL
+    good = E.Closure(C.init_params(22), norms)
+    ref, rst = good.infer(f, ub, fallback=E.INFER_UNCHECKED)
+    ref = ref.clone()
+    for mode in (E.INFER_CHECK, E.INFER_FALLBACK):
+        got, gst = good.infer(f, ub, fallback=mode, u=du)
+        assert good.fell_back == 0
+        assert torch.equal(got, ref) and torch.equal(gst, rst)
+
+
+def test_set_params_rejects_non_finite_blob(E):
+    norms = np.concatenate([np.zeros(10), np.ones(10), np.zeros(6), np.ones(6)])
+    cl = E.Closure(C.init_params(3), norms)
+    blob = cl.get_params()
+    bad = np.frombuffer(blob, dtype=np.uint8).copy()      # FP32 weights come first
+    bad[4 * 17:4 * 18] = np.frombuffer(np.float32(np.nan).tobytes(), dtype=np.uint8)
+    with pytest.raises(E.ElesError) as ei:
+        cl.set_params(bad.tobytes())
+    assert ei.value.status == E.ELES_ENUMERIC
+    assert cl.get_params() == blob
