@@ -12,7 +12,7 @@
 // wall the node across it is the mirror of the first interior node,
 // carrying the field's parity under the extension of eq. (7), so the wall
 // row is 0 for even fields and f_1/(y_1 - y_0) (resp. -f_{n-2}/...) for odd.
-#include "k_gemm.cuh"
+#include "k_gemm.h"
 
 namespace eles {
 namespace {
