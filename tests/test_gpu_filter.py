@@ -77,7 +77,7 @@ def _rel(a, b, y):
 
 
 @pytest.mark.parametrize("name,over", GRIDS)
-@pytest.mark.parametrize("mode,tol", [("fp32", 2e-6), ("bf16x3", 3e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("mode,tol", [("fp32", 2e-6), ("bf16x3", 2e-5), ("bf16", 2e-2)])
 def test_filter_fields_match_oracle(E, name, over, mode, tol):
     cfg = _cfg(name, over)
     y = synth.ygrid(cfg.ny, cfg.ykind, cfg.stretch)
@@ -164,14 +164,47 @@ def test_sgs_stress_matches_oracle(E, label, base, over, seed, route, xz):
     # plane statistics: the library's FP64 sums of its own outputs ...
     mine = np.concatenate([R.plane_mean(ub), R.plane_mean(tau)])
     assert np.max(np.abs(st - mine)) < 1e-12 * (1 + np.abs(mine).max())
-    # ... and against the oracle's profiles: per plane, the mean of the
-    # field difference is bounded by its rms (Cauchy-Schwarz)
-    mine_f = np.concatenate([ub, tau])
-    ref_f = np.concatenate([rub, rtau])
-    ref = np.concatenate([R.plane_mean(rub), R.plane_mean(rtau)])
-    for q in range(9):
-        rms = np.sqrt(np.mean((mine_f[q] - ref_f[q]) ** 2, axis=(0, 2)))
-        assert np.all(np.abs(st[q] - ref[q]) <= rms * (1 + 1e-9) + 1e-14), q
+    # ... and the profiles against the oracle's
+    check_profiles(u, ops, y, st, rub, rtau)
+
+
+def profile_tolerances(u, ops, y):
+    """Tolerance of the eq. (14)-form error of each <tau_ij>(y). The rounding
+    argument of fp32_tolerances applied to plane means: every output point
+    carries an error of about 2^-24 |F(u_i' u_j')|, and its plane mean is at
+    most the plane's rms of that, so the bound is max(1e-5, 8 kp_ij 2^-24)
+    with kp_ij = |rms_xz F(u_i' u_j')| / |<tau_ij>| (profile norms)."""
+    u = u.astype(np.float64)
+    v = u.copy()
+    v[0] -= R.plane_mean(u[0])[None, :, None]
+    _, tau = R.sgs_stress(u, ops)
+    tol = []
+    w = R.trapezoid(y)
+    for k, (i, j) in enumerate(R.PAIRS):
+        big = R.filt(v[i] * v[j], R.PARITY[i] * R.PARITY[j], ops)
+        big_rms = np.sqrt(R.plane_mean(big ** 2))
+        ref = R.plane_mean(tau[k])
+        kp = math.sqrt(np.sum(w * big_rms ** 2) / np.sum(w * ref ** 2))
+        tol.append(max(1e-5, 8 * kp * 2.0 ** -24))
+    return tol
+
+
+def check_profiles(u, ops, y, st, rub, rtau):
+    """Every plane-mean profile of the library against the oracle's. <ubar_1>
+    and the six <tau_ij> in the eq. (14) form (Sec. 4.1) within
+    profile_tolerances; <ubar_2> and <ubar_3> vanish for the generator's
+    fields (zero-mean modes), so they are compared absolutely, within 1e-6
+    of the field's rms."""
+    ptol = profile_tolerances(u, ops, y)
+    e = R.profile_error(st[0], R.plane_mean(rub[0]), y)
+    assert e < 1e-5, ("<ubar_1>", e)
+    for k in (1, 2):
+        rms = math.sqrt(np.mean(rub[k] ** 2))
+        assert np.max(np.abs(st[k] - R.plane_mean(rub[k]))) < 1e-6 * rms, ("<ubar>", k)
+    for k in range(6):
+        e = R.profile_error(st[3 + k], R.plane_mean(rtau[k]), y)
+        print("profile tau", R.PAIRS[k], f"{e:.2e} (tol {ptol[k]:.1e})", flush=True)
+        assert e < ptol[k], ("<tau>", R.PAIRS[k], e, ptol[k])
 
 
 # Wide stencils (x/z half-widths above 16): the matrix-core wide kernel
@@ -206,6 +239,7 @@ def test_sgs_wide_stencils(E, label, base, over, seed, tail, xz):
         print(label, f"m=({f.layout.mx},{f.layout.mz})", "tau", R.PAIRS[k], f"{err:.2e} (tol {tol[k]:.1e})",
               flush=True)
         assert err < tol[k], ("tau", k, err)
+    check_profiles(u, ops, y, st, rub, rtau)
 
 
 def test_sgs_dns192_full_size(E):
@@ -224,6 +258,8 @@ def test_sgs_dns192_full_size(E):
         assert max(errs) < 1e-5, errs
         ref12 = R.plane_mean(rtau[1])
         assert R.profile_error(st[4], ref12, y) < 1e-5
+        if seed == 0:
+            check_profiles(u, ops, y, st, rub, rtau)
 
 
 def test_sgs_deterministic_and_invariants(E):
@@ -246,15 +282,35 @@ def test_sgs_deterministic_and_invariants(E):
     assert tr.min() > -1e-6 * scale
 
 
-@pytest.mark.parametrize("mode,tol", [("bf16x3", 1e-4), ("bf16", 5e-2)])
-def test_sgs_reduced_precision_y_pass(E, mode, tol):
-    cfg = synth.config("dns192", nx=64, nz=64)
+@pytest.mark.parametrize("mode", ["bf16x3", "bf16"])
+def test_sgs_reduced_precision_y_pass(E, mode):
+    """The reduced-precision y arithmetics on the full 192 x 129 x 192
+    channel (the benchmark grid). The BF16x3 split holds each operand to
+    2^-16 relative (two BF16 of 8 significant bits each) instead of FP32's
+    2^-24, so the FP32 rule max(1e-5, 8 kappa 2^-24) becomes
+    max(2e-5, kappa_ij 2^-16); the 2e-5 target itself is checked on the
+    512 x 257 x 512 and 1024 x 385 x 768 configurations, where BF16x3 is the
+    configured arithmetic. Plain BF16 (8 bits) is reported, within 5e-2."""
+    cfg = synth.config("dns192")
     y, u, ub, tau, st, _ = _sgs_case(E, cfg, 0, mode=mode)
     ops = R.Operators.from_config(cfg)
     rub, rtau = R.sgs_stress(u.astype(np.float64), ops)
     errs = [_rel(ub[k], rub[k], y) for k in range(3)] + [_rel(tau[k], rtau[k], y) for k in range(6)]
     print(mode, " ".join(f"{e:.2e}" for e in errs), flush=True)
-    assert max(errs) < tol
+    if mode == "bf16":
+        assert max(errs) < 5e-2
+        return
+    u64 = u.astype(np.float64)
+    v = u64.copy()
+    v[0] -= R.plane_mean(u64[0])[None, :, None]
+    for k in range(3):
+        assert errs[k] < 2e-5, ("ubar", k, errs[k])
+    for k, (i, j) in enumerate(R.PAIRS):
+        big = R.filt(v[i] * v[j], R.PARITY[i] * R.PARITY[j], ops)
+        kap = math.sqrt(np.sum(big ** 2) / np.sum(rtau[k] ** 2))
+        tol = max(2e-5, kap * 2.0 ** -16)
+        print("bf16x3 tau", R.PAIRS[k], f"{errs[3 + k]:.2e} (kappa {kap:.1f}, tol {tol:.1e})", flush=True)
+        assert errs[3 + k] < tol, ("tau", R.PAIRS[k], errs[3 + k], tol)
 
 
 def test_profile_pass_mask_times_only_the_selected_passes(E):

@@ -46,7 +46,7 @@ def _run(E, cfg, u, mode, tail, rows):
 
 def test_dns512_rows_y_precision(E):
     """512 x 257 x 512, 1e-8 tail, rows 0, 1, 4, 16, 64, 128, 192, 256:
-    FP32 within 2e-5 on every output, BF16x3 within 1e-4, BF16 within 5e-2
+    FP32 within 1e-5 on every output, BF16x3 within 2e-5, BF16 within 5e-2
     (relative L2 over the rows)."""
     cfg = synth.config("dns512")
     tail = 1e-8
@@ -54,7 +54,7 @@ def test_dns512_rows_y_precision(E):
     rows = [0, 1, 4, 16, 64, 128, 192, 256]
     ops = R.Operators.from_config(cfg, tail_tol=tail)
     rub, rtau = R.sgs_rows(u, ops, rows)
-    limits = {"fp32": 2e-5, "bf16x3": 1e-4, "bf16": 5e-2}
+    limits = {"fp32": 1e-5, "bf16x3": 2e-5, "bf16": 5e-2}
     for mode, lim in limits.items():
         gub, gtau, groups = _run(E, cfg, u, mode, tail, rows)
         errs = [_rel(gub[k], rub[k]) for k in range(3)] + [_rel(gtau[k], rtau[k]) for k in range(6)]
@@ -67,18 +67,28 @@ def test_dns512_rows_y_precision(E):
             assert groups > 0
 
 
-def test_dns1024_rows_production_shape(E):
-    """1024 x 385 x 768 at the 1e-8 tail, FP32 path (LDS-staged y pass), rows
-    at both walls, in the near-wall band and at the centre: every output
-    within 2e-5 relative L2."""
+@pytest.fixture(scope="module")
+def dns1024_case():
+    """One 1024 x 385 x 768 snapshot and the oracle on its selected rows."""
     cfg = synth.config("dns1024")
     tail = 1e-8
     y, u = synth.make_snapshot(cfg, synth.SEEDS["dns1024"][0])
     rows = [0, 1, 6, 48, 192, 336, 383, 384]
     ops = R.Operators.from_config(cfg, tail_tol=tail)
     rub, rtau = R.sgs_rows(u, ops, rows)
-    gub, gtau, groups = _run(E, cfg, u, "fp32", tail, rows)
-    assert groups > 0
+    return cfg, tail, u, rows, rub, rtau
+
+
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+def test_dns1024_rows_production_shape(E, dns1024_case, mode):
+    """1024 x 385 x 768 at the 1e-8 tail, rows at both walls, in the near-wall
+    band and at the centre: FP32 (LDS-staged y pass) within 1e-5 relative L2
+    on every output, BF16x3 (the production pipeline's y arithmetic) within
+    2e-5."""
+    cfg, tail, u, rows, rub, rtau = dns1024_case
+    gub, gtau, groups = _run(E, cfg, u, mode, tail, rows)
+    if mode == "fp32":
+        assert groups > 0
     errs = [_rel(gub[k], rub[k]) for k in range(3)] + [_rel(gtau[k], rtau[k]) for k in range(6)]
-    print("dns1024 fp32: per output " + " ".join(f"{e:.1e}" for e in errs), flush=True)
-    assert max(errs) < 2e-5, errs
+    print(f"dns1024 {mode}: per output " + " ".join(f"{e:.1e}" for e in errs), flush=True)
+    assert max(errs) < {"fp32": 1e-5, "bf16x3": 2e-5}[mode], errs
