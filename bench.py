@@ -77,25 +77,50 @@ def pass_model(cfg, f, ops_nnz):
     }
 
 
+def host_cpu():
+    """nproc (the cores this process may use) and the CPU model name."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return len(os.sched_getaffinity(0)), model
+
+
+def _time_oracle(fn, budget_s, max_reps=64):
+    reps, t0 = 0, time.perf_counter()
+    out = None
+    while True:
+        out = fn()
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= max_reps:
+            return reps, el, out
+
+
 def cpu_baseline(cfg, u_host, budget_s):
-    """The FP64 oracle timed on the host cores over whole snapshots."""
-    from threadpoolctl import threadpool_info
+    """The FP64 oracle timed on the host cores over whole snapshots: with the
+    BLAS threads it uses by default, then on one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     import numpy as np
     from oracle import filter_ref as R
     ops = R.Operators.from_config(cfg)
     u64 = u_host.astype(np.float64)
-    reps, t0 = 0, time.perf_counter()
-    out = None
-    while True:
-        out = R.sgs_stress(u64, ops)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 64:
-            break
+    reps, el, out = _time_oracle(lambda: R.sgs_stress(u64, ops), budget_s)
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    with threadpool_limits(limits=1):
+        reps1, el1, _ = _time_oracle(lambda: R.sgs_stress(u64, ops), budget_s / 4, max_reps=8)
+    nproc, model = host_cpu()
     return {"value": cfg.points * reps / el, "unit": "points/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"{reps} full {cfg.nx}x{cfg.ny}x{cfg.nz} snapshot(s), FP64 dense sums, {el:.1f} s"}, out
+            "sample": f"{reps} full {cfg.nx}x{cfg.ny}x{cfg.nz} snapshot(s), FP64 dense sums, {el:.1f} s",
+            "nproc": nproc, "cpu_model": model,
+            "one_thread": {"value": cfg.points * reps1 / el1, "unit": "points/s",
+                           "sample": f"{reps1} snapshot(s), {el1:.1f} s"}}, out
 
 
 def dfilter_pass_model(cfg, nf=9, products=True):
@@ -154,17 +179,12 @@ def dfilter_cpu_baseline(cfg, u_host, budget_s):
     from oracle import dfilter_ref as D
     ops = D.DOperators.from_config(cfg)
     u64 = u_host.astype(np.float64)
-    reps, t0 = 0, time.perf_counter()
-    out = None
-    while True:
-        out = D.sgs_stress(u64, ops)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 64:
-            break
+    reps, el, out = _time_oracle(lambda: D.sgs_stress(u64, ops), budget_s)
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    nproc, model = host_cpu()
     return {"value": cfg.points * reps / el, "unit": "points/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{reps} full {cfg.nx}x{cfg.ny}x{cfg.nz} snapshot(s), FP64 FFT + Thomas, {el:.1f} s"}, out
+            "sample": f"{reps} full {cfg.nx}x{cfg.ny}x{cfg.nz} snapshot(s), FP64 FFT + Thomas, {el:.1f} s",
+            "nproc": nproc, "cpu_model": model}, out
 
 
 def les_grid_measure(cfg, eles, torch, ubar, tau, steps):
@@ -352,11 +372,10 @@ def main():
     seeds = synth.SEEDS.get(a.workload, [0, 1, 2, 3])[: a.snapshots]
     while len(seeds) < a.snapshots:
         seeds.append(seeds[-1] + 1)
-    hosts, us = [], []
+    us = []
     for s in seeds:
-        y, u = synth.make_snapshot(cfg, s)
-        hosts.append(u)
-        us.append(torch.from_numpy(u).to(dev))
+        y, terms = synth.snapshot_factors(cfg, s)
+        us.append(synth.assemble_on_device(cfg, terms, dev))
     f = eles.Filter.from_config(cfg, tail_tol=a.tail, ygemm=a.ygemm, device=dev)
     matrix_xz = a.xz == "matrix" and f.layout.xz_waves > 0
     if f.layout.xz_waves > 0:
@@ -407,7 +426,8 @@ def main():
     passes = {k: {"us_avg": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in prof_all.items()}
     traffic_rec = counters.read_summary(os.path.join(ROOT, "profiles", f"hbm_traffic_{a.workload}.md"))
     staged = f.layout.y_groups > 0 and a.ygemm == "fp32"
-    names = {"xz": "k_xzm" if matrix_xz else "k_xz", "y": "k_ys" if staged else "k_y"}
+    xz_name = ("k_xzw" if f.layout.xz_wide else "k_xzm") if matrix_xz else "k_xz"
+    names = {"xz": xz_name, "y": "k_ys" if staged else "k_y_" + a.ygemm}
     roofs = {}
     for k in ("xz", "y"):
         t_k = prof[k][0] / 1e3 / max(prof[k][1], 1)
@@ -439,7 +459,7 @@ def main():
     cpu = None
     parity = None
     if a.cpu_seconds > 0:
-        cpu, (rub, rtau) = cpu_baseline(cfg, hosts[0], a.cpu_seconds)
+        cpu, (rub, rtau) = cpu_baseline(cfg, us[0].cpu().numpy(), a.cpu_seconds)
         from oracle import filter_ref as R
         f.sgs_stress(us[0], ubar[0], tau[0], stats[0])
         torch.cuda.synchronize()

@@ -31,7 +31,12 @@ _DF = ["k_dfilt.hip", "eles_internal.h"]
 KERNELS = {
     "k_xz": ("k_xz", ["k_xz.hip", "eles_internal.h"]),
     "k_xzm": ("k_xzm", ["k_xzm.hip", "eles_internal.h"]),
+    "k_xzw": ("k_xzw", ["k_xzw.hip", "eles_internal.h"]),
     "k_ys": ("k_ys", ["k_ys.hip", "eles_internal.h"]),
+    # the direct y pass of the stress, by arithmetic (FP32 / BF16 / BF16x3)
+    "k_y<true, 0>": ("k_y_fp32", ["k_y.hip", "eles_internal.h"]),
+    "k_y<true, 1>": ("k_y_bf16", ["k_y.hip", "eles_internal.h"]),
+    "k_y<true, 2>": ("k_y_bf16x3", ["k_y.hip", "eles_internal.h"]),
     # differential filter: transforms (x with the products, z), y solves, epilogue
     "k_dfwd_lds<false, true>": ("dfilter_xf", _DF),
     "k_dfwd_lds<true, false>": ("dfilter_zf", _DF),

@@ -28,7 +28,7 @@ import numpy as np
 
 __all__ = [
     "ChannelConfig", "CONFIGS", "config", "ygrid", "mean_profile",
-    "snapshot_factors", "make_snapshot", "assemble", "SEEDS",
+    "snapshot_factors", "make_snapshot", "assemble", "assemble_on_device", "SEEDS",
 ]
 
 
@@ -193,6 +193,25 @@ def assemble(cfg: ChannelConfig, terms, dtype=np.float32, x_chunk: int = 64) -> 
             for (g, f) in terms[c]:
                 acc += g[None, :, None] * f[x0:x1, None, :]
             u[c, x0:x1] = acc.astype(dtype)
+    return u
+
+
+def assemble_on_device(cfg: ChannelConfig, terms, device):
+    """assemble() into a torch FP32 tensor on `device`: the same FP64 sums in
+    the same order (one multiply and one add per term), rounded to FP32,
+    so the values equal assemble()'s. For the large grids, whose host
+    assembly takes seconds."""
+    import torch
+    u = torch.empty((3, cfg.nx, cfg.ny, cfg.nz), dtype=torch.float32, device=device)
+    for c in range(3):
+        gs = [torch.from_numpy(np.ascontiguousarray(g)).to(device) for g, _ in terms[c]]
+        fs = [torch.from_numpy(np.ascontiguousarray(f)).to(device) for _, f in terms[c]]
+        for x0 in range(0, cfg.nx, 64):
+            x1 = min(cfg.nx, x0 + 64)
+            acc = torch.zeros((x1 - x0, cfg.ny, cfg.nz), dtype=torch.float64, device=device)
+            for g, f in zip(gs, fs):
+                acc += g[None, :, None] * f[x0:x1, None, :]
+            u[c, x0:x1] = acc.to(torch.float32)
     return u
 
 
