@@ -368,15 +368,23 @@ size_t closure_state_bytes(void);
 /* Create a closure in the caller's state buffer. params: host
  * [ELES_CLOSURE_NPARAM] initial weights; norms: host FP64 [32] = feature
  * means [10], feature standard deviations [10], target means [6], target
- * standard deviations [6]. Waits for its copies. Errors: EINVAL, ENOSPACE,
- * ENUMERIC (non-finite values, non-positive deviations), EHIP. */
+ * standard deviations [6]. gm_coef: host FP64 [3] or NULL. With c =
+ * gm_coef the closure adds the gradient model, the leading term of the
+ * small-width expansion of the filtered stress (cf. the invertible filters
+ * of Sec. 2.1), G_ij = sum_k c_k (d ubar_i/dx_k)(d ubar_j/dx_k), to the
+ * network: tau = G + mu + sd N(x'), and training fits N to the
+ * standardised remainder (tau - G - mu) / sd. For a filter of widths D_k,
+ * c_k = D_k^2 / 12; NULL (or zeros) is the plain network. Waits for its
+ * copies. Errors: EINVAL, ENOSPACE, ENUMERIC (non-finite values,
+ * non-positive deviations, negative coefficients), EHIP. */
 int32_t closure_create(void *state, size_t state_bytes, const float *params, const double *norms,
-                       hipStream_t stream, eles_closure *out);
+                       const double *gm_coef, hipStream_t stream, eles_closure *out);
 
 /* Adam steps taken so far (-1 for a null handle). */
 int64_t closure_step(eles_closure c);
 
-/* Checkpoint blob: FP32 weights, Adam m and v, FP64 norms, int64 step.
+/* Checkpoint blob: FP32 weights, Adam m and v, FP64 norms, int64 step,
+ * FP64 gradient-model coefficients [3].
  * closure_get_params copies the state into the host blob on the stream
  * (after the work already queued there) and waits for the stream.
  * closure_set_params validates the blob on the host (ENUMERIC: non-finite

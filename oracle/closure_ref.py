@@ -24,6 +24,14 @@ checked against.
   its derivative is Phi(x) + x phi(x), phi the normal density. Inputs and
   targets are standardised with training-set means and standard
   deviations.
+* Physics term: the closure adds the gradient model, the leading term of
+  the small-width expansion of the stress of a filter with second moments
+  sigma_k^2 (cf. the invertible-filter discussion of Sec. 2.1),
+  G_ij = sum_k c_k (d ubar_i / d x_k) (d ubar_j / d x_k), c_k = sigma_k^2 =
+  Delta_k^2 / 12. The prediction is tau = G + mu + sd * N((x - m) / s), N
+  the network, (m, s) and (mu, sd) the feature and stress moments; the
+  network learns the standardised remainder (tau - G - mu) / sd. With
+  c = 0 it is the plain network.
 * Loss: mean over the batch and the six outputs of the squared error.
 * Adam (Kingma & Ba 2015) with bias correction, no weight decay.
 * Minibatch sampler: SplitMix64 (Steele, Lea & Flood 2014), output n of a
@@ -84,6 +92,43 @@ def features(ubar: np.ndarray, y: np.ndarray, lx: float, lz: float) -> np.ndarra
         out[3 * i + 2] = spectral_derivative(ubar[i], lz, 2)
     out[9] = (1.0 - np.abs(y))[None, :, None] * np.ones((nx, 1, nz))
     return out
+
+
+# ------------------------------------------------------------ physics term
+
+PAIRS = ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))
+
+
+def gradient_model(feat: np.ndarray, coef) -> np.ndarray:
+    """G_ij = sum_k coef[k] g_ik g_jk with g_ik = feat[3 i + k], over the
+    leading axis of feat [10, ...]; returns [6, ...] in the order 11, 12,
+    13, 22, 23, 33."""
+    feat = np.asarray(feat, dtype=np.float64)
+    out = np.zeros((6,) + feat.shape[1:])
+    for q, (i, j) in enumerate(PAIRS):
+        for k in range(3):
+            out[q] += coef[k] * feat[3 * i + k] * feat[3 * j + k]
+    return out
+
+
+def widths_coef(delta_x: float, delta_y: float, delta_z: float):
+    """c_k = Delta_k^2 / 12, the second moment of the filter in direction k."""
+    return (delta_x ** 2 / 12.0, delta_y ** 2 / 12.0, delta_z ** 2 / 12.0)
+
+
+def predict(theta, feat: np.ndarray, norms: np.ndarray, coef=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """The closure's stress [6, ...] from features [10, ...]: G + mu + sd N(x')."""
+    feat = np.asarray(feat, dtype=np.float64)
+    shape = feat.shape[1:]
+    x = (feat.reshape(10, -1).T - norms[:10]) / norms[10:20]
+    y = forward(theta, x) * norms[26:32] + norms[20:26]
+    return y.T.reshape((6,) + shape) + gradient_model(feat, coef)
+
+
+def standard_targets(tau: np.ndarray, feat: np.ndarray, norms: np.ndarray, coef=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """[N, 6] training targets (tau - G - mu) / sd of fields tau [6, ...]."""
+    r = np.asarray(tau, dtype=np.float64) - gradient_model(feat, coef)
+    return (r.reshape(6, -1).T - norms[20:26]) / norms[26:32]
 
 
 # --------------------------------------------------------------------- MLP

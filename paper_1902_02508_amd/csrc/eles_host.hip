@@ -596,6 +596,7 @@ struct eles_closure_s {
   eles::ClosureView c;
   double *norm64;     // device copy of the standardisation moments
   long step;          // Adam steps taken so far
+  double gm_coef[3];  // gradient-model coefficients (0: the plain network)
 };
 
 namespace {
@@ -625,6 +626,23 @@ bool valid_norms(const double *n) {
     if (!(n[eles::kMlpIn + k] > 0.0)) return false;
   for (int k = 0; k < eles::kMlpOut; ++k)
     if (!(n[2 * eles::kMlpIn + eles::kMlpOut + k] > 0.0)) return false;
+  return true;
+}
+
+// Gradient-model coefficients of a handle (NULL: none), host and kernel copies.
+void set_coef(eles_closure_s *h, const double *c) {
+  bool any = false;
+  for (int k = 0; k < 3; ++k) {
+    h->gm_coef[k] = c ? c[k] : 0.0;
+    h->c.gmc[k] = (float)h->gm_coef[k];
+    any = any || h->gm_coef[k] != 0.0;
+  }
+  h->c.use_gm = any ? 1 : 0;
+}
+
+bool valid_coef(const double *c) {
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(c[k]) || c[k] < 0.0) return false;
   return true;
 }
 
@@ -704,10 +722,11 @@ extern "C" {
 size_t closure_state_bytes(void) { return closure_layout(nullptr); }
 
 int32_t closure_create(void *state, size_t state_bytes, const float *params, const double *norms,
-                       hipStream_t stream, eles_closure *out) {
+                       const double *gm_coef, hipStream_t stream, eles_closure *out) {
   if (!out) return ELES_EINVAL;
   *out = nullptr;
   if (!state || !params || !norms || !aligned16(state)) return ELES_EINVAL;
+  if (gm_coef && !valid_coef(gm_coef)) return ELES_ENUMERIC;
   size_t off[C_END];
   const size_t need = closure_layout(off);
   if (state_bytes < need) return ELES_ENOSPACE;
@@ -738,6 +757,7 @@ int32_t closure_create(void *state, size_t state_bytes, const float *params, con
   c.isc = n32 + 2 * I + 2 * O;
   c.ish = n32 + 2 * I + 3 * O;
   h->step = 0;
+  set_coef(h, gm_coef);
   float nrm[kNrm32];
   derive_nrm32(norms, nrm);
   const size_t pbytes = (size_t)eles::kMlpNParam * 4;
@@ -756,7 +776,7 @@ int32_t closure_create(void *state, size_t state_bytes, const float *params, con
 
 int64_t closure_step(eles_closure c) { return c ? c->step : -1; }
 
-size_t closure_blob_bytes(void) { return (size_t)3 * eles::kMlpNParam * 4 + kNorm * 8 + 8; }
+size_t closure_blob_bytes(void) { return (size_t)3 * eles::kMlpNParam * 4 + kNorm * 8 + 8 + 3 * 8; }
 
 int32_t closure_get_params(eles_closure c, void *blob, size_t bytes, hipStream_t stream) {
   if (!c || !blob || bytes < closure_blob_bytes()) return ELES_EINVAL;
@@ -772,6 +792,7 @@ int32_t closure_get_params(eles_closure c, void *blob, size_t bytes, hipStream_t
     return ELES_EHIP;
   int64_t st = c->step;
   std::memcpy(b + 3 * pb + kNorm * 8, &st, 8);
+  std::memcpy(b + 3 * pb + kNorm * 8 + 8, c->gm_coef, 3 * 8);
   return ELES_OK;
 }
 
@@ -787,6 +808,9 @@ int32_t closure_set_params(eles_closure c, const void *blob, size_t bytes, hipSt
   int64_t st;
   std::memcpy(&st, b + 3 * pb + kNorm * 8, 8);
   if (st < 0) return ELES_EINVAL;
+  double coef[3];
+  std::memcpy(coef, b + 3 * pb + kNorm * 8 + 8, 3 * 8);
+  if (!valid_coef(coef)) return ELES_ENUMERIC;
   float nrm[kNrm32];
   derive_nrm32(n, nrm);
   // stream-ordered after the work already queued on the handle; the call
@@ -800,6 +824,7 @@ int32_t closure_set_params(eles_closure c, const void *blob, size_t bytes, hipSt
       eles::launch_shadows(c->c, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
     return ELES_EHIP;
   c->step = st;
+  set_coef(c, coef);
   return ELES_OK;
 }
 

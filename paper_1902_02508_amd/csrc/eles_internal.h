@@ -172,6 +172,11 @@ struct ClosureView {
   const float *fsc, *fsh;                       // standardised feature = f * fsc + fsh
   const float *tsc, *tsh;                       // standardised target  = t * tsc + tsh
   const float *isc, *ish;                       // target = y * isc + ish
+  // gradient-model term added to the prediction: G_ij = sum_k gmc[k]
+  // g_ik g_jk over the raw features g_ik = feat[3 i + k]; gmc = 0 (and
+  // use_gm = 0) leaves the plain network
+  float gmc[3];
+  int use_gm;
 };
 struct TrainData {
   const float *feat, *tau;   // [nsnap][10][npts], [nsnap][6][npts]

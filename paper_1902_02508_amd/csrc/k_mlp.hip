@@ -69,6 +69,28 @@ __global__ void __launch_bounds__(256) k_sample(uint64_t seed, long step, int ba
 }
 
 // Draw the minibatch of `step` and gather standardised features and targets.
+// G_ij = sum_k c_k g_ik g_jk for the six pairs (11, 12, 13, 22, 23, 33) of
+// the raw gradient features g_ik = feat(3 i + k); zeros without the term.
+template <class Feat>
+__device__ inline void gradient_model(const ClosureView &c, Feat feat, float *gm) {
+  if (!c.use_gm) {
+#pragma unroll
+    for (int o = 0; o < kMlpOut; ++o) gm[o] = 0.0f;
+    return;
+  }
+  float g[9];
+#pragma unroll
+  for (int f = 0; f < 9; ++f) g[f] = feat(f);
+  constexpr int pi[kMlpOut] = {0, 0, 0, 1, 1, 2}, pj[kMlpOut] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+  for (int o = 0; o < kMlpOut; ++o) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc = fmaf(c.gmc[k] * g[3 * pi[o] + k], g[3 * pj[o] + k], acc);
+    gm[o] = acc;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_gather(ClosureView c, TrainData d, uint64_t seed, long step, int batch,
                                                 uint16_t *x0, uint16_t *x0t, float *tb) {
   const int b = blockIdx.x * 256 + threadIdx.x;
@@ -92,8 +114,10 @@ __global__ void __launch_bounds__(256) k_gather(ClosureView c, TrainData d, uint
 #pragma unroll
   for (int q = 0; q < K1 / 8; ++q)
     row[q] = make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
+  float gm[kMlpOut];
+  gradient_model(c, [&](int f) { return fs[(uint64_t)f * d.npts]; }, gm);
 #pragma unroll
-  for (int o = 0; o < kMlpOut; ++o) tb[(long)b * 8 + o] = ts[(uint64_t)o * d.npts] * c.tsc[o] + c.tsh[o];
+  for (int o = 0; o < kMlpOut; ++o) tb[(long)b * 8 + o] = (ts[(uint64_t)o * d.npts] - gm[o]) * c.tsc[o] + c.tsh[o];
 }
 
 // ---------------------------------------------------------------- products
@@ -389,6 +413,27 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
       for (int e = 0; e < 4; ++e) w[e] = g_bf16x2(xs[2 * e], xs[2 * e + 1]);
       xb = __builtin_bit_cast(gus8, w);
     }
+    // gradient-model term of this lane's outputs 4 grp + r, from the raw
+    // features of the current tile (lanes of group 0 hold features 0..7,
+    // of group 1 features 8, 9; the others are exchanged)
+    float gmr[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (c.use_gm) {
+      const float t8 = __shfl(fv[0], 16 + col, 64);
+      float g[9];
+#pragma unroll
+      for (int e = 3; e < 8; ++e) {
+        const float o = __shfl(fv[e], col, 64);
+        g[e] = grp == 0 ? fv[e] : o;
+      }
+      g[0] = fv[0];
+      g[1] = fv[1];
+      g[2] = fv[2];
+      g[8] = grp == 0 ? t8 : fv[0];
+      float G[kMlpOut];
+      gradient_model(c, [&](int f) { return g[f]; }, G);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gmr[r] = grp == 0 ? G[r] : (r < 2 ? G[4 + r] : 0.0f);
+    }
     fetch(tile + stride);
     // the four bias values of accumulator t of a layer whose biases start
     // at sb + base: rows 16 t + 4 grp .. + 3
@@ -430,7 +475,7 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int o = 4 * grp + r;
-          if (o < kMlpOut && pok) out[(long)o * npts + p] = y[r] * c.isc[o] + c.ish[o];
+          if (o < kMlpOut && pok) out[(long)o * npts + p] = y[r] * c.isc[o] + c.ish[o] + gmr[r];
         }
       }
     }

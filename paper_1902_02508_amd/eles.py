@@ -104,7 +104,7 @@ _SIG = {
     "dfilter_profile_begin": (_I, [_P, _I, ctypes.c_uint32]),
     "dfilter_profile_end": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)]),
     "closure_state_bytes": (_S, []),
-    "closure_create": (_I, [_P, _S, _P, _P, _P, ctypes.POINTER(_P)]),
+    "closure_create": (_I, [_P, _S, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "closure_step": (ctypes.c_int64, [_P]),
     "closure_blob_bytes": (_S, []),
     "closure_get_params": (_I, [_P, _P, _S, _P]),
@@ -374,9 +374,9 @@ def closure_state_bytes() -> int:
     return lib.closure_state_bytes()
 
 
-def closure_create(state_ptr, state_bytes, params_host, norms_host, stream):
+def closure_create(state_ptr, state_bytes, params_host, norms_host, coef_host, stream):
     h = _P()
-    _check(lib.closure_create(state_ptr, state_bytes, params_host, norms_host, stream, ctypes.byref(h)),
+    _check(lib.closure_create(state_ptr, state_bytes, params_host, norms_host, coef_host, stream, ctypes.byref(h)),
            "closure_create")
     return h
 
@@ -470,7 +470,9 @@ def moments(data: torch.Tensor) -> torch.Tensor:
 class Closure:
     """A closure handle; state, workspace and norms live on the current device."""
 
-    def __init__(self, params: np.ndarray, norms: np.ndarray, device="cuda"):
+    def __init__(self, params: np.ndarray, norms: np.ndarray, device="cuda", gm_coef=None):
+        """gm_coef: the gradient-model coefficients c_k = Delta_k^2 / 12 (three
+        values), or None for the plain network."""
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
@@ -479,10 +481,17 @@ class Closure:
         n = np.ascontiguousarray(norms, dtype=np.float64)
         if p.size != NPARAM or n.size != 32:
             raise ValueError("params must hold 9414 values and norms 32")
+        c = None
+        if gm_coef is not None:
+            c = np.ascontiguousarray(gm_coef, dtype=np.float64)
+            if c.size != 3:
+                raise ValueError("gm_coef must hold 3 values")
+        self._coef = c
         self.state = torch.empty(closure_state_bytes(), dtype=torch.uint8, device=dev)
         self.h = closure_create(_ptr(self.state), self.state.numel(), p.ctypes.data_as(_P),
-                                n.ctypes.data_as(_P), _stream())
+                                n.ctypes.data_as(_P), c.ctypes.data_as(_P) if c is not None else None, _stream())
         self._ws = torch.empty(0, dtype=torch.uint8, device=dev)
+        self.fell_back = 0
 
     # bound at class creation: module globals may already be gone when an
     # object is collected at interpreter exit

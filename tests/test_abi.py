@@ -110,15 +110,15 @@ def test_closure_validation_without_device(eles):
     p = np.zeros(eles.NPARAM, dtype=np.float32)
     n = np.ones(32)
     assert eles.closure_state_bytes() > 9414 * 12
-    assert eles.lib.closure_create(None, 1 << 20, p.ctypes.data, n.ctypes.data, None, C.byref(h)) == eles.ELES_EINVAL
-    assert eles.lib.closure_create(0x1000, 16, p.ctypes.data, n.ctypes.data, None, C.byref(h)) == eles.ELES_ENOSPACE
+    assert eles.lib.closure_create(None, 1 << 20, p.ctypes.data, n.ctypes.data, None, None, C.byref(h)) == eles.ELES_EINVAL
+    assert eles.lib.closure_create(0x1000, 16, p.ctypes.data, n.ctypes.data, None, None, C.byref(h)) == eles.ELES_ENOSPACE
     bad = p.copy()
     bad[5] = np.nan
     big = eles.closure_state_bytes()
-    assert eles.lib.closure_create(0x1000, big, bad.ctypes.data, n.ctypes.data, None, C.byref(h)) == eles.ELES_ENUMERIC
+    assert eles.lib.closure_create(0x1000, big, bad.ctypes.data, n.ctypes.data, None, None, C.byref(h)) == eles.ELES_ENUMERIC
     n0 = n.copy()
     n0[12] = 0.0            # a feature with zero spread
-    assert eles.lib.closure_create(0x1000, big, p.ctypes.data, n0.ctypes.data, None, C.byref(h)) == eles.ELES_ENUMERIC
+    assert eles.lib.closure_create(0x1000, big, p.ctypes.data, n0.ctypes.data, None, None, C.byref(h)) == eles.ELES_ENUMERIC
     assert eles.closure_train_workspace_bytes(33) == 0
     assert eles.closure_train_workspace_bytes(0) == 0
     assert eles.closure_train_workspace_bytes(65536) > 65536 * 64
@@ -133,7 +133,10 @@ def test_closure_validation_without_device(eles):
     assert eles.lib.closure_get_params(None, blob, len(blob), None) == eles.ELES_EINVAL
     assert eles.lib.closure_set_params(None, blob, len(blob), None) == eles.ELES_EINVAL
     assert eles.lib.closure_step(None) == -1
-    assert eles.closure_blob_bytes() == 3 * 9414 * 4 + 32 * 8 + 8
+    neg = np.array([0.1, -1e-3, 0.2])
+    assert eles.lib.closure_create(0x1000, big, p.ctypes.data, n.ctypes.data, neg.ctypes.data, None,
+                                   C.byref(h)) == eles.ELES_ENUMERIC
+    assert eles.closure_blob_bytes() == 3 * 9414 * 4 + 32 * 8 + 8 + 3 * 8
 
 
 def _ddesc(eles, nx=16, ny=17, nz=12, lx=2.0, lz=1.0, y=None, a=0.1):

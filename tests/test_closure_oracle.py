@@ -173,3 +173,49 @@ def test_moments():
     a = np.random.default_rng(0).standard_normal((2, 50, 4)) * np.array([1.0, 3.0])[:, None, None] + 2
     mu, sd = C.moments(a)
     assert np.allclose(mu, a.reshape(2, -1).mean(1)) and np.allclose(sd, a.reshape(2, -1).std(1))
+
+
+def test_gradient_model_small_width_limit():
+    """G is the leading term of the filtered stress: for a single smooth x
+    mode and a narrow Gaussian, tau_11 / G_11 -> 1 (the oracle filter's
+    exact stress, independent of the closure code)."""
+    from oracle import filter_ref as R
+    nx, ny, nz, lx, lz = 256, 9, 8, 2 * np.pi, 1.0
+    y = synth.ygrid(ny, "uniform")
+    x = np.arange(nx) * lx / nx
+    u = np.zeros((3, nx, ny, nz))
+    u[0] = np.sin(x)[:, None, None] * np.ones((1, ny, nz))
+    ratios = []
+    for d in (0.8, 0.4):
+        ops = R.Operators(nx, ny, nz, lx, lz, y, d, 1e-3, 1e-3)
+        ub, tau = R.sgs_stress(u, ops)
+        feat = C.features(ub, y, lx, lz)
+        g = C.gradient_model(feat, C.widths_coef(d, 1e-3, 1e-3))
+        ratios.append(np.max(np.abs(tau[0] - g[0])) / np.max(np.abs(tau[0])))
+    # relative remainder O(Delta^2): halves the width, quarters the remainder
+    assert ratios[1] < 0.3 * ratios[0] and ratios[1] < 1e-2, ratios
+
+
+def test_gradient_model_pairs_and_symmetry():
+    rng = np.random.default_rng(2)
+    feat = rng.standard_normal((10, 7))
+    c = (0.3, 0.02, 0.1)
+    g = C.gradient_model(feat, c)
+    grad = feat[:9].reshape(3, 3, 7)            # [i][k][point]
+    full = np.einsum("k,ikp,jkp->ijp", np.array(c), grad, grad)
+    for q, (i, j) in enumerate(C.PAIRS):
+        assert np.allclose(g[q], full[i, j]) and np.allclose(g[q], full[j, i])
+    assert np.all(g[[0, 3, 5]] >= 0)            # positive semidefinite diagonal
+
+
+def test_predict_and_targets_invert_each_other():
+    rng = np.random.default_rng(3)
+    feat = rng.standard_normal((10, 4, 5, 3))
+    th = C.init_params(4)
+    norms = np.concatenate([rng.standard_normal(10), rng.uniform(0.5, 2, 10),
+                            rng.standard_normal(6), rng.uniform(0.5, 2, 6)])
+    c = (0.1, 0.2, 0.05)
+    tau = C.predict(th, feat, norms, c)
+    t = C.standard_targets(tau, feat, norms, c)
+    x = (feat.reshape(10, -1).T - norms[:10]) / norms[10:20]
+    assert np.allclose(t, C.forward(th, x), atol=1e-12)

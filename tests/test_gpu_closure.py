@@ -92,12 +92,16 @@ def _emulated_forward(theta, xs):
     return h
 
 
-def test_inference_matches_oracle(E):
-    """The network against the FP64 reference with the exact GELU. Tolerance:
-    the BF16 roundings (2e-3 against a BF16 emulation of the reference, 3e-2
-    against FP64) plus the effect of the kernels' GELU fit on these inputs,
-    the FP64 network with the fit against the same network with x Phi(x)
-    (the fit itself is bounded by 2.4e-4 on the CPU)."""
+@pytest.mark.parametrize("physics", [False, True])
+def test_inference_matches_oracle(E, physics):
+    """The closure against the FP64 reference with the exact GELU, as the
+    plain network and with the gradient-model term (coefficients Delta_k^2
+    / 12 of the grid's filter). Tolerance: the BF16 roundings (2e-3 against
+    a BF16 emulation of the reference, 3e-2 against FP64) plus the effect
+    of the kernels' GELU fit on these inputs, the FP64 network with the fit
+    against the same network with x Phi(x) (the fit itself is bounded by
+    2.4e-4 on the CPU). The gradient-model term is FP32 arithmetic on the
+    raw features and adds no BF16 rounding."""
     cfg = synth.config("dns192", nx=32, nz=32, ny=33)
     y, u = synth.make_snapshot(cfg, 4)
     f = E.Filter.from_config(cfg)
@@ -105,19 +109,22 @@ def test_inference_matches_oracle(E):
     feat = _host(E.features(f, ub))
     taun = _host(tau)
     norms = _norms(feat, taun)
+    coef = C.widths_coef(cfg.delta_x, cfg.delta_y, cfg.delta_z) if physics else (0.0, 0.0, 0.0)
     theta = C.init_params(11) * 2.0
-    cl = E.Closure(theta, norms)
+    cl = E.Closure(theta, norms, gm_coef=coef if physics else None)
     pred, st = cl.infer(f, ub)
     pred = _host(pred)
     xs = ((feat.reshape(10, -1).T - norms[:10]) / norms[10:20])
     th32 = theta.astype(np.float32).astype(np.float64)
+    gm = C.gradient_model(feat, coef).reshape(6, -1).T
     ref_std = C.forward(th32, xs)
-    ref = ref_std * norms[26:32] + norms[20:26]
-    emu = _emulated_forward(theta, xs) * norms[26:32] + norms[20:26]
+    ref = ref_std * norms[26:32] + norms[20:26] + gm
+    assert np.allclose(ref.T.reshape((6,) + feat.shape[1:]), C.predict(th32, feat, norms, coef))
+    emu = _emulated_forward(theta, xs) * norms[26:32] + norms[20:26] + gm
     fit_rel = _rel(kernel_gelu.forward(C.unpack, th32, xs) * norms[26:32], ref_std * norms[26:32])
     got = pred.reshape(6, -1).T
     e_exact, e_emu = _rel(got, ref), _rel(got, emu)
-    print(f"inference rel error vs FP64 {e_exact:.2e}, vs BF16 emulation {e_emu:.2e}; "
+    print(f"inference (physics {physics}) rel error vs FP64 {e_exact:.2e}, vs BF16 emulation {e_emu:.2e}; "
           f"effect of the GELU fit {fit_rel:.2e}", flush=True)
     assert e_emu < 2e-3 + fit_rel and e_exact < 3e-2 + fit_rel
     assert np.allclose(_host(st), pred.mean(axis=(1, 3)), rtol=1e-10, atol=1e-14)
@@ -136,16 +143,20 @@ def _dataset(E, n_snap=2):
     return cfg, torch.stack(feats), torch.stack(taus)
 
 
-def test_gradient_matches_oracle(E):
+@pytest.mark.parametrize("physics", [False, True])
+def test_gradient_matches_oracle(E, physics):
     """One Adam step with beta1 = beta2 = 0 and a large eps moves every weight
-    by -lr g / (|g| + eps), which is inverted for the gradient g. Tolerance
-    2e-2: BF16 storage of activations and of GELU' (2^-8 each) plus the
-    kernels' GELU-derivative fit (within 5e-3 of Phi(x) + x phi(x))."""
+    by -lr g / (|g| + eps), which is inverted for the gradient g. With the
+    gradient-model term the targets are the standardised remainders
+    (tau - G - mu) / sd. Tolerance 2e-2: BF16 storage of activations and of
+    GELU' (2^-8 each) plus the kernels' GELU-derivative fit (within 5e-3 of
+    Phi(x) + x phi(x))."""
     cfg, feat, tau = _dataset(E)
     fh, th = _host(feat), _host(tau)
     norms = _norms(np.moveaxis(fh, 1, 0), np.moveaxis(th, 1, 0))
+    coef = C.widths_coef(cfg.delta_x, cfg.delta_y, cfg.delta_z) if physics else (0.0, 0.0, 0.0)
     theta0 = C.init_params(5)
-    cl = E.Closure(theta0, norms)
+    cl = E.Closure(theta0, norms, gm_coef=coef if physics else None)
     batch, seed, lr, eps = 1024, 42, 1e3, 1e4
     cl.train(feat, tau, steps=1, batch=batch, seed=seed, lr=lr, beta1=0.0, beta2=0.0, eps=eps)
     t1 = cl.theta().astype(np.float64)
@@ -155,11 +166,13 @@ def test_gradient_matches_oracle(E):
     npts = fh[0, 0].size
     idx = C.sample_indices(seed, 0, batch, 2 * npts).astype(np.int64)
     s, p = idx // npts, idx % npts
-    xs = (fh.reshape(2, 10, -1)[s, :, p] - norms[:10]) / norms[10:20]
-    ts = (th.reshape(2, 6, -1)[s, :, p] - norms[20:26]) / norms[26:32]
+    fsel = fh.reshape(2, 10, -1)[s, :, p]                     # [batch, 10]
+    tsel = th.reshape(2, 6, -1)[s, :, p]                      # [batch, 6]
+    xs = (fsel - norms[:10]) / norms[10:20]
+    ts = C.standard_targets(tsel.T, fsel.T, norms, coef)
     loss, g_ref = C.loss_and_grad(t0, xs, ts)
     err = _rel(g_gpu, g_ref)
-    print(f"gradient rel L2 error {err:.2e} (loss {loss:.4f})", flush=True)
+    print(f"gradient (physics {physics}) rel L2 error {err:.2e} (loss {loss:.4f})", flush=True)
     assert err < 2e-2
 
 
