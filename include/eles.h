@@ -408,6 +408,20 @@ size_t closure_moments_workspace_bytes(int32_t nchan);
 int32_t closure_moments(const float *data, int32_t nchan, int32_t nsnap, int64_t npts, double *out, void *ws,
                         size_t ws_bytes, hipStream_t stream);
 
+/* closure_moments for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid
+ * allocation): no workspace argument. Its partial sums live in a static
+ * device array of ELES_MOMENTS_NOALLOC_MAX_CHAN x 1024 doubles (512 KiB)
+ * that each GPU the library runs on holds until the process ends; the
+ * call allocates nothing. The stream must belong to the current device.
+ * Results are bit for bit those of closure_moments. Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (from two streams
+ * or threads) race and must be serialised by the caller. Errors: EINVAL
+ * (null pointers, nchan, nsnap or npts < 1), ENOSPACE (nchan above
+ * ELES_MOMENTS_NOALLOC_MAX_CHAN: beyond the static array), EHIP. */
+#define ELES_MOMENTS_NOALLOC_MAX_CHAN 64
+int32_t closure_moments_noalloc(const float *data, int32_t nchan, int32_t nsnap, int64_t npts, double *out,
+                                hipStream_t stream);
 
 /* Adam training on minibatches drawn from nsnap snapshots of features
  * (device [nsnap][10][npts]) and exact stresses (device [nsnap][6][npts]);

@@ -112,6 +112,7 @@ _SIG = {
     "closure_features": (_I, [_P, _P, _P, _P]),
     "closure_moments_workspace_bytes": (_S, [_I]),
     "closure_moments": (_I, [_P, _I, _I, ctypes.c_int64, _P, _P, _S, _P]),
+    "closure_moments_noalloc": (_I, [_P, _I, _I, ctypes.c_int64, _P, _P]),
     "closure_train_workspace_bytes": (_S, [_I]),
     "closure_train": (_I, [_P, _P, _P, _I, ctypes.c_int64, _P, _P, _P, _S, _P]),
     "closure_infer_workspace_bytes": (_S, [_P, _I]),
@@ -413,6 +414,13 @@ def closure_moments(data_ptr, nchan, nsnap, npts, out_ptr, ws_ptr, ws_bytes, str
     _check(lib.closure_moments(data_ptr, nchan, nsnap, npts, out_ptr, ws_ptr, ws_bytes, stream), "closure_moments")
 
 
+MOMENTS_NOALLOC_MAX_CHAN = 64
+
+
+def closure_moments_noalloc(data_ptr, nchan, nsnap, npts, out_ptr, stream):
+    _check(lib.closure_moments_noalloc(data_ptr, nchan, nsnap, npts, out_ptr, stream), "closure_moments_noalloc")
+
+
 def closure_train_workspace_bytes(batch: int) -> int:
     return lib.closure_train_workspace_bytes(batch)
 
@@ -464,6 +472,19 @@ def moments(data: torch.Tensor) -> torch.Tensor:
     out = torch.empty((2, C), dtype=torch.float64, device=data.device)
     ws = torch.empty(closure_moments_workspace_bytes(C), dtype=torch.uint8, device=data.device)
     closure_moments(_ptr(data), C, S, npts, _ptr(out), _ptr(ws), ws.numel(), _stream())
+    return out
+
+
+def moments_noalloc(data: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """moments() through the entry point that takes no workspace; out, if
+    given, is the caller's [2][C] FP64 result buffer."""
+    if data.dtype != torch.float32 or not data.is_contiguous():
+        raise ValueError("data must be contiguous float32")
+    S, C = data.shape[0], data.shape[1]
+    npts = data[0, 0].numel()
+    if out is None:
+        out = torch.empty((2, C), dtype=torch.float64, device=data.device)
+    closure_moments_noalloc(_ptr(data), C, S, npts, _ptr(out), _stream())
     return out
 
 
