@@ -57,27 +57,66 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libeles.so; returns the library path."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build of the same
+# library, for the CPU tests of the validation paths (no GPU needed): each
+# -fsanitize= applies to the host compilation only; device code is built as
+# usual. Loaded with the clang ASan runtime preloaded.
+SAN_DIR = os.path.join(HERE, "_build_san")
+SAN_LIB = os.path.join(SAN_DIR, "libeles_san.so")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def asan_runtime() -> str:
+    """The clang ASan runtime shared library (to preload)."""
+    import glob
+    root = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    hits = sorted(glob.glob(os.path.join(root, "llvm", "lib", "clang", "*", "lib", "linux",
+                                         "libclang_rt.asan-x86_64.so")))
+    if not hits:
+        raise RuntimeError("clang ASan runtime not found")
+    return hits[-1]
+
+
+def _compile_all(build_dir, extra_all, verbose):
+    os.makedirs(build_dir, exist_ok=True)
     cc = hipcc()
     objs = []
     jobs = []
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         for src in sources():
-            obj = os.path.join(BUILD_DIR, os.path.basename(src)[:-4] + ".o")
+            obj = os.path.join(build_dir, os.path.basename(src)[:-4] + ".o")
             objs.append(obj)
             extra = EXTRA.get(os.path.basename(src), [])
-            jobs.append(ex.submit(_run, [cc, *FLAGS, *extra, "-c", src, "-o", obj]))
+            jobs.append(ex.submit(_run, [cc, *FLAGS, *extra, *extra_all, "-c", src, "-o", obj]))
         for j in jobs:
             out = j.result()
             if verbose and out.strip():
                 print(out)
+    return cc, objs
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source and link libeles.so; returns the library path."""
+    cc, objs = _compile_all(BUILD_DIR, [], verbose)
     tmp = LIB + ".tmp"
     _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 
 
+def build_sanitized(verbose: bool = False) -> str:
+    """The host-sanitized library (SAN_LIB); returns its path."""
+    cc, objs = _compile_all(SAN_DIR, SAN_FLAGS, verbose)
+    tmp = SAN_LIB + ".tmp"
+    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-shared-libsan", "-Xarch_host",
+          "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", *objs, "-o", tmp])
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitized" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

@@ -16,7 +16,9 @@ import numpy as np
 import torch  # load torch's HIP runtime first so the library binds to the same one
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libeles.so")
+# ELES_LIB selects another build of the same library (the host-sanitized one
+# of the CPU sanitizer test)
+LIB_PATH = os.environ.get("ELES_LIB") or os.path.join(_HERE, "libeles.so")
 
 ELES_OK, ELES_EINVAL, ELES_ENOSPACE, ELES_EHIP, ELES_ENUMERIC, ELES_ENOTSUP = range(6)
 YGEMM = {"fp32": 0, "bf16": 1, "bf16x3": 2}
