@@ -6,7 +6,14 @@ A step is one exact-stress evaluation (filtered velocity, the six stress
 components and their plane averages) of one 192 x 129 x 192 channel
 snapshot; four seeded snapshots stay resident in HBM and are cycled. The
 timed region is K steps bracketed by device synchronisations; HIP events on
-the library's stream time every pass inside it. Prints one JSON line.
+the library's stream time the dominant pass inside it. Prints one JSON line.
+
+Beside the headline (unless --skip-extras): the stress on the LES2 / LES4
+grids; the production shape 1024 x 385 x 768 (one snapshot in HBM, BF16x3
+and FP32 y passes, rooflines tied to the committed counter summaries); and
+the learned closure, trained on exact stresses of 192 x 129 x 192
+snapshots, judged on held-out snapshots and on the production snapshot by
+the <tau_12>(y) profile error, and timed against the exact path there.
 """
 from __future__ import annotations
 
@@ -44,8 +51,14 @@ def parse():
                    help="x/z pass on the matrix cores (where it covers the grid) or the vector units")
     p.add_argument("--snapshots", type=int, default=4)
     p.add_argument("--skip-extras", action="store_true",
-                   help="time only the stress (no LES-grid, inverse-filter or error measurements): "
-                        "for profiler runs whose per-kernel figures must cover the stress alone")
+                   help="time only the stress (no LES-grid, production-shape, closure, inverse-filter or "
+                        "error measurements): for profiler runs whose per-kernel figures must cover the "
+                        "stress alone")
+    p.add_argument("--production-steps", type=int, default=5,
+                   help="timed steps of the 1024x385x768 production block")
+    p.add_argument("--closure-train", type=int, default=32,
+                   help="192x129x192 training snapshots of the closure block")
+    p.add_argument("--closure-steps", type=int, default=20000, help="Adam steps of the closure block")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the oracle CPU baseline (0 disables it)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -350,34 +363,20 @@ def main_differential(a):
     print(json.dumps(line), flush=True)
 
 
-def main():
-    a = parse()
-    if a.copy_calibration:
-        copy_calibration(a.copy_calibration)
-        return
-    if a.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
-              "(snapshots are independent: run one process per GPU)", file=sys.stderr)
-        sys.exit(2)
-    if a.filter == "differential":
-        main_differential(a)
-        return
-    import numpy as np
-    import torch
-    from paper_1902_02508_amd import counters, eles, synth
-
+def measure_exact(cfg, ygemm, tail, xz, snapshots, steps, warmup, seeds, torch, eles, synth, counters,
+                  np, traffic_name, log):
+    """Time the exact stress path (sgs_stress: shift, x/z, y, statistics) on
+    snapshots resident in HBM. Per-pass durations come from a loop of their
+    own (an event pair between two kernels adds a few microseconds); the
+    timed region brackets only the dominant pass with events, so its
+    roofline is measured live."""
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    cfg = synth.config(a.workload)
-    seeds = synth.SEEDS.get(a.workload, [0, 1, 2, 3])[: a.snapshots]
-    while len(seeds) < a.snapshots:
-        seeds.append(seeds[-1] + 1)
     us = []
-    for s in seeds:
+    for s in seeds[:snapshots]:
         y, terms = synth.snapshot_factors(cfg, s)
         us.append(synth.assemble_on_device(cfg, terms, dev))
-    f = eles.Filter.from_config(cfg, tail_tol=a.tail, ygemm=a.ygemm, device=dev)
-    matrix_xz = a.xz == "matrix" and f.layout.xz_waves > 0
+    f = eles.Filter.from_config(cfg, tail_tol=tail, ygemm=ygemm, device=dev)
+    matrix_xz = xz == "matrix" and f.layout.xz_waves > 0
     if f.layout.xz_waves > 0:
         f.set_xz(matrix_xz)
     ns = len(us)
@@ -389,34 +388,28 @@ def main():
         k = i % ns
         f.sgs_stress(us[k], ubar[k], tau[k], stats[k])
 
-    for i in range(a.warmup):
+    for i in range(warmup):
         step(i)
     torch.cuda.synchronize()
-    print(f"warmup done ({a.warmup} steps)", file=sys.stderr, flush=True)
-
-    # per-pass durations of every kernel, in a loop of their own: an event
-    # pair between two kernels adds a few microseconds, so the timed region
-    # brackets only the dominant pass
-    eles.filter_profile_begin(f.h, a.steps)
-    for i in range(a.steps):
+    log(f"warmup done ({warmup} steps)")
+    eles.filter_profile_begin(f.h, steps)
+    for i in range(steps):
         step(i)
     prof_all = eles.filter_profile_end(f.h)
     dom = max(("xz", "y"), key=lambda k: prof_all[k][0] / max(prof_all[k][1], 1))
 
-    eles.filter_profile_begin(f.h, a.steps, passes=[eles.PASS_NAMES.index(dom)])
+    eles.filter_profile_begin(f.h, steps, passes=[eles.PASS_NAMES.index(dom)])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(a.steps):
+    for i in range(steps):
         step(i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof_dom = eles.filter_profile_end(f.h)
     el = t1 - t0
-    ms_per_step = 1e3 * el / a.steps
-    value = cfg.points * a.steps / el
-    print(f"timed {a.steps} steps: {ms_per_step:.4f} ms/step", file=sys.stderr, flush=True)
-    # the dominant pass as timed live in the timed region; the others from
-    # the per-pass loop
+    ms_per_step = 1e3 * el / steps
+    value = cfg.points * steps / el
+    log(f"timed {steps} steps: {ms_per_step:.4f} ms/step")
     prof = dict(prof_all)
     prof[dom] = prof_dom[dom]
 
@@ -424,10 +417,10 @@ def main():
     nnz = float(np.count_nonzero(ops["wp"])) / cfg.ny
     model = pass_model(cfg, f, nnz)
     passes = {k: {"us_avg": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in prof_all.items()}
-    traffic_rec = counters.read_summary(os.path.join(ROOT, "profiles", f"hbm_traffic_{a.workload}.md"))
-    staged = f.layout.y_groups > 0 and a.ygemm == "fp32"
+    traffic_rec = counters.read_summary(os.path.join(ROOT, "profiles", f"hbm_traffic_{traffic_name}.md"))
+    staged = f.layout.y_groups > 0 and ygemm == "fp32"
     xz_name = ("k_xzw" if f.layout.xz_wide else "k_xzm") if matrix_xz else "k_xz"
-    names = {"xz": xz_name, "y": "k_ys" if staged else "k_y_" + a.ygemm}
+    names = {"xz": xz_name, "y": "k_ys" if staged else "k_y_" + ygemm}
     roofs = {}
     for k in ("xz", "y"):
         t_k = prof[k][0] / 1e3 / max(prof[k][1], 1)
@@ -451,8 +444,125 @@ def main():
         r["timed"] = "timed region" if k == dom else "per-pass loop"
         tr = counters.current(traffic_rec, names[k])
         r["traffic"] = tr["bytes"] if tr else None
+        if tr:
+            r["traffic_source_sha256"] = tr["source_sha256"]
         roofs[k] = r
-    roof = roofs[dom]
+    return dict(f=f, us=us, ubar=ubar, tau=tau, stats=stats, value=value, ms_per_step=ms_per_step,
+                roofs=roofs, dom=dom, passes=passes, matrix_xz=matrix_xz, ns=ns)
+
+
+def production_block(a, torch, eles, synth, counters, np, log):
+    """The production shape, 1024 x 385 x 768 (one snapshot resident in
+    HBM): the exact path with the BF16x3 y pass (the configured production
+    arithmetic) and with FP32, per-pass rooflines tied to the committed
+    counter summaries."""
+    cfg = synth.config("dns1024")
+    seeds = synth.SEEDS["dns1024"]
+    out = {"workload": f"channel {cfg.nx}x{cfg.ny}x{cfg.nz} exact filtered velocity + tau_ij",
+           "snapshots": 1, "steps": a.production_steps}
+    keep = None
+    for mode in ("bf16x3", "fp32"):
+        r = measure_exact(cfg, mode, a.tail, "matrix", 1, a.production_steps, 1, seeds, torch, eles, synth,
+                          counters, np, "dns1024" if mode == "fp32" else "dns1024_bf16x3", log)
+        out[mode] = {"points_per_s": r["value"], "ms_per_step": r["ms_per_step"], "roofline": r["roofs"][r["dom"]],
+                     "rooflines": r["roofs"], "passes": r["passes"]}
+        if mode == "fp32":
+            keep = r
+        else:
+            del r
+        torch.cuda.empty_cache()
+    return out, cfg, keep
+
+
+def closure_block(a, torch, eles, synth, np, prod_cfg, prod, log):
+    """The learned closure (row a8/a9): trained on exact stresses of
+    192 x 129 x 192 snapshots, judged on held-out ones and on the production
+    snapshot by the eq. (14)-form error of <tau_12>(y) against the exact
+    path's FP64 statistics, and timed against the exact path."""
+    from paper_1902_02508_amd import experiment as X
+    dev = torch.device("cuda:0")
+    cfg = synth.config("dns192")
+    f = eles.Filter.from_config(cfg, tail_tol=a.tail, device=dev)
+    t0 = time.perf_counter()
+    feats, taus = X.build_dataset(f, cfg, synth.SEEDS["train"][:a.closure_train], dev, log=log)
+    fm, tm = eles.moments(feats).cpu().numpy(), eles.moments(taus).cpu().numpy()
+    norms = np.concatenate([fm[0], fm[1], tm[0], tm[1]])
+    cl = eles.Closure(X.init_params(1), norms, device=dev, gm_coef=X.widths_coef(cfg))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lh = cl.train(feats, taus, steps=a.closure_steps, batch=65536, seed=1, lr=1e-3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    loss = lh.cpu().numpy()
+    del feats, taus
+    torch.cuda.empty_cache()
+    rows = X.evaluate(cl, f, cfg, synth.SEEDS["heldout"], dev, baseline=X.gradient_model_closure(cfg, norms, dev))
+    res = {"train": {"snapshots": a.closure_train, "steps": a.closure_steps, "batch": 65536,
+                     "seconds": t2 - t1, "dataset_seconds": t1 - t0,
+                     "loss_first": float(loss[:10].mean()), "loss_last": float(loss[-100:].mean())},
+           "heldout": {"snapshots": len(rows),
+                       "tau12_profile_error": float(np.mean([r["tau12_profile_error"] for r in rows])),
+                       "tau12_profile_error_gradient_model":
+                           float(np.mean([r["tau12_profile_error_gradient_model"] for r in rows])),
+                       "tau12_profile_error_zero": 1.0,
+                       "pointwise_rel_l2": [float(np.mean([r["pointwise_rel_l2"][q] for r in rows]))
+                                            for q in range(6)],
+                       "pointwise_rel_l2_gradient_model": [
+                           float(np.mean([r["pointwise_rel_l2_gradient_model"][q] for r in rows])) for q in range(6)]}}
+    if prod is not None:
+        # closure inference on the production snapshot's filtered velocity,
+        # the exact path (FP32 y pass) as the judge
+        pf, ub, st = prod["f"], prod["ubar"][0], prod["stats"][0]
+        pred = torch.empty((6,) + pf.shape, dtype=torch.float32, device=dev)
+        pst = torch.empty((6, prod_cfg.ny), dtype=torch.float64, device=dev)
+        for mode in (eles.INFER_UNCHECKED, eles.INFER_CHECK):
+            cl.infer(pf, ub, pred, pst, fallback=mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.production_steps):
+                cl.infer(pf, ub, pred, pst, fallback=mode)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            key = "closure_points_per_s" if mode == eles.INFER_CHECK else "closure_points_per_s_unchecked"
+            res.setdefault("production", {})[key] = prod_cfg.points * a.production_steps / el
+        y = synth.ygrid(prod_cfg.ny, prod_cfg.ykind, prod_cfg.stretch)
+        p = res["production"]
+        p["tau12_profile_error"] = X.profile_error(pst[1].cpu().numpy(), st[4].cpu().numpy(), y)
+        p["exact_fp32_points_per_s"] = prod["value"]
+        p["speedup_vs_exact_fp32"] = p["closure_points_per_s"] / prod["value"]
+        p["workload"] = f"channel {prod_cfg.nx}x{prod_cfg.ny}x{prod_cfg.nz}, seed {synth.SEEDS['dns1024'][0]}"
+    return res
+
+
+def main():
+    a = parse()
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
+              "(snapshots are independent: run one process per GPU)", file=sys.stderr)
+        sys.exit(2)
+    if a.filter == "differential":
+        main_differential(a)
+        return
+    import numpy as np
+    import torch
+    from paper_1902_02508_amd import counters, eles, synth
+
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = synth.config(a.workload)
+    seeds = list(synth.SEEDS.get(a.workload, [0, 1, 2, 3]))
+    while len(seeds) < a.snapshots:
+        seeds.append(seeds[-1] + 1)
+    traffic = a.workload if a.ygemm == "fp32" else f"{a.workload}_{a.ygemm}"
+    m = measure_exact(cfg, a.ygemm, a.tail, a.xz, a.snapshots, a.steps, a.warmup, seeds, torch, eles, synth,
+                      counters, np, traffic, log)
+    f, us, ubar, tau, stats = m["f"], m["us"], m["ubar"], m["tau"], m["stats"]
 
     les = None if a.skip_extras else les_grid_measure(cfg, eles, torch, ubar, tau, a.steps)
 
@@ -469,25 +579,38 @@ def main():
         parity = max([R.rel_l2(gu[k], rub[k], yv) for k in range(3)] +
                      [R.rel_l2(gt[k], rtau[k], yv) for k in range(6)])
 
+    head = {"value": m["value"], "ms_per_step": m["ms_per_step"], "roofline": m["roofs"][m["dom"]],
+            "rooflines": m["roofs"], "passes": m["passes"], "matrix_xz": m["matrix_xz"], "ns": m["ns"],
+            "layout": f.layout}
+    production = closure = None
+    if not a.skip_extras and a.workload == "dns192":
+        del m, f, us, ubar, tau, stats
+        torch.cuda.empty_cache()
+        production, pcfg, prod = production_block(a, torch, eles, synth, counters, np, log)
+        closure = closure_block(a, torch, eles, synth, np, pcfg, prod, log)
+        del prod
+        torch.cuda.empty_cache()
+
+    lay = head["layout"]
     line = {
-        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step,
+        "metric": METRIC, "value": head["value"], "unit": "points/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "fp32" if a.ygemm == "fp32" else a.ygemm, "data": "synthetic",
         "config": {"workload": f"channel {cfg.nx}x{cfg.ny}x{cfg.nz} exact filtered velocity + tau_ij",
                    "box": f"{cfg.lx:.4f}x2x{cfg.lz:.4f}", "widths": [cfg.delta_x, cfg.delta_y, cfg.delta_z],
-                   "tail_tol": a.tail, "ygemm": a.ygemm, "xz": "matrix" if matrix_xz else "vector",
-                   "snapshots": ns,
-                   "stencil_half_widths": [f.layout.mx, f.layout.mz], "parallelism": "none"},
-        "roofline": roof,
-        "rooflines": roofs,
+                   "tail_tol": a.tail, "ygemm": a.ygemm, "xz": "matrix" if head["matrix_xz"] else "vector",
+                   "snapshots": head["ns"], "stencil_half_widths": [lay.mx, lay.mz], "parallelism": "none"},
+        "roofline": head["roofline"],
+        "rooflines": head["rooflines"],
         "cpu_baseline": cpu,
-        "passes": passes,
+        "passes": head["passes"],
         "max_rel_l2_vs_oracle": parity,
         "les_grid": les,
+        "production": production,
+        "closure": closure,
     }
     print(json.dumps(line), flush=True)
-
 
 if __name__ == "__main__":
     main()
