@@ -191,17 +191,23 @@ __global__ void __launch_bounds__(kT) k_mean(OpsView v, const float *u1) {
   const int sx = v.nx / ns;
   const long cnt = (long)ns * v.nz;
   double part = 0.0;
-  // element t = q nz + z, walked with 32-bit (q, z) steps of kT
-  int q = (int)threadIdx.x / v.nz, z = (int)threadIdx.x % v.nz;
-  const int dq = kT / v.nz, dz = kT % v.nz;
-  while (q < ns) {
-    part += (double)u1[((size_t)(q * sx) * v.ny + j) * v.nz + z];
-    q += dq;
-    z += dz;
-    if (z >= v.nz) {
-      z -= v.nz;
-      ++q;
+  // element t = q nz + z of slab row q, t = threadIdx + kT k: eight
+  // elements are requested together (independent loads), then summed in
+  // order
+  const int cnt_i = ns * v.nz;
+  for (int t0 = (int)threadIdx.x; t0 < cnt_i; t0 += 8 * kT) {
+    float w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int t = t0 + k * kT;
+      const bool ok = t < cnt_i;
+      const int tc = ok ? t : 0;   // in-bounds address for the unused lanes
+      const int q = tc / v.nz, z = tc - q * v.nz;
+      const float val = u1[((size_t)(q * sx) * v.ny + j) * v.nz + z];
+      w[k] = ok ? val : 0.0f;
     }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) part += (double)w[k];
   }
   double s = block_sum(part, red);
   if (threadIdx.x == 0) {
