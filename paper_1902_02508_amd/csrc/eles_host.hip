@@ -62,7 +62,7 @@ struct Plan {
 
 enum {
   O_Y, O_WP, O_WM, O_WX64, O_WZ64, O_SHIFT, O_WX32, O_WZ32, O_A32, O_AHI, O_ALO, O_RB, O_PROF,
-  O_DX32, O_DXHI, O_DXLO, O_DXB, O_DZHI, O_DZLO, O_DY32, O_DYHI, O_DYLO, O_DYB, O_END
+  O_DX32, O_DXHI, O_DXLO, O_DXB, O_DZHI, O_DZLO, O_DY32, O_DYHI, O_DYLO, O_DYB, O_TWX, O_TWZ, O_END
 };
 static_assert(O_END <= 32, "Plan::off holds 32 regions");
 
@@ -102,7 +102,7 @@ int32_t plan_filter(const eles_filter_desc *d, Plan *p) {
       (size_t)eles::tap_pad_len((int)mx) * 4, (size_t)eles::tap_pad_len((int)mz) * 4,
       4 * mk * 4, 4 * mk * 2, 4 * mk * 2, (size_t)p->mpad * 2 * 4, (size_t)p->mpad * 3 * 4,
       mkx * 4, mkx * 2, mkx * 2, (size_t)p->mpx * 2 * 4, mkz * 2, mkz * 2,
-      2 * mk * 4, 2 * mk * 2, 2 * mk * 2, (size_t)p->mpad * 2 * 4};
+      2 * mk * 4, 2 * mk * 2, 2 * mk * 2, (size_t)p->mpad * 2 * 4, (size_t)d->nx * 8, (size_t)d->nz * 8};
   size_t o = 0;
   for (int k = 0; k < O_END; ++k) {
     p->off[k] = o;
@@ -172,6 +172,10 @@ eles::GradView make_grad_view(const eles_filter_desc *d, const Plan &p, char *st
     g.dylo[w] = (uint16_t *)(st + p.off[O_DYLO]) + w * mk;
   }
   g.dyband = (int *)(st + p.off[O_DYB]);
+  eles::sder_plan(d->nx, d->lx, false, &g.sx);
+  eles::sder_plan(d->nz, d->lz, true, &g.sz);
+  g.sx.tw = (float2 *)(st + p.off[O_TWX]);
+  g.sz.tw = (float2 *)(st + p.off[O_TWZ]);
   return g;
 }
 
@@ -390,7 +394,8 @@ int32_t filter_setup(const eles_filter_desc *desc, void *state, size_t state_byt
   if (hipMemcpyAsync(f->v.y64, f->y.data(), desc->ny * sizeof(double), hipMemcpyHostToDevice, stream) !=
           hipSuccess ||
       eles::launch_build_ops(f->v, stream) != hipSuccess ||
-      eles::launch_build_grad_ops(f->gv, f->v.y64, stream) != hipSuccess) {
+      eles::launch_build_grad_ops(f->gv, f->v.y64, stream) != hipSuccess ||
+      eles::sder_setup(f->gv.sx, stream) != hipSuccess || eles::sder_setup(f->gv.sz, stream) != hipSuccess) {
     delete f;
     return ELES_EHIP;
   }
@@ -828,14 +833,12 @@ int32_t closure_set_params(eles_closure c, const void *blob, size_t bytes, hipSt
   return ELES_OK;
 }
 
-int32_t closure_features(eles_filter f, const float *ubar, float *feat, hipStream_t stream) {
-  if (!f || !ubar || !feat || !aligned16(ubar) || !aligned16(feat)) return ELES_EINVAL;
+// d/dx by the dense spectral operator through the y-pass kernel, the field
+// seen as one [nx] x [ny nz] slab (BF16x3 products)
+int32_t dense_dx(eles_filter f, const float *ubar, float *feat, hipStream_t stream) {
   const size_t n = f->npts;
-  if (overlap(ubar, 3 * n * 4, feat, 10 * n * 4)) return ELES_EINVAL;
   const int nx = f->d.nx, ny = f->d.ny, nz = f->d.nz;
   const eles::GradView &g = f->gv;
-  // d/dx: the dense spectral operator along x, the field seen as one
-  // [nx] x [ny nz] slab
   eles::YArgs ya = y_args(f);
   for (int w = 0; w < 4; ++w) {
     ya.a32[w] = g.dx32;
@@ -859,7 +862,22 @@ int32_t closure_features(eles_filter f, const float *ubar, float *feat, hipStrea
   ya.out_fs = 3 * n;
   ya.out_xs = 0;
   ya.out_ks = (size_t)ny * nz;
-  if (eles::launch_y(ya, false, ELES_YGEMM_BF16X3, stream) != hipSuccess) return ELES_EHIP;
+  return eles::launch_y(ya, false, ELES_YGEMM_BF16X3, stream) == hipSuccess ? ELES_OK : ELES_EHIP;
+}
+
+int32_t closure_features(eles_filter f, const float *ubar, float *feat, hipStream_t stream) {
+  if (!f || !ubar || !feat || !aligned16(ubar) || !aligned16(feat)) return ELES_EINVAL;
+  const size_t n = f->npts;
+  if (overlap(ubar, 3 * n * 4, feat, 10 * n * 4)) return ELES_EINVAL;
+  const int nx = f->d.nx, ny = f->d.ny, nz = f->d.nz;
+  const eles::GradView &g = f->gv;
+  // d/dx: fast transforms along x where nx factors into 2, 3 and 5, else
+  // the dense spectral operator, the field seen as one [nx] x [ny nz] slab
+  if (g.sx.nrad) {
+    if (eles::launch_sder(g, false, ubar, feat, (long)(3 * n), stream) != hipSuccess) return ELES_EHIP;
+  } else if (dense_dx(f, ubar, feat, stream) != ELES_OK) {
+    return ELES_EHIP;
+  }
   // d/dy: three-point difference with the parities of (u1, u2, u3),
   // streamed along each column (grids of three or more rows)
   if (ny >= 3) {
@@ -885,8 +903,13 @@ int32_t closure_features(eles_filter f, const float *ubar, float *feat, hipStrea
     yb.out_ks = nz;
     if (eles::launch_y(yb, false, ELES_YGEMM_FP32, stream) != hipSuccess) return ELES_EHIP;
   }
-  // d/dz: rows times the transposed spectral operator
-  if (eles::launch_dz(g, ubar, feat + 2 * n, (long)(3 * n), stream) != hipSuccess) return ELES_EHIP;
+  // d/dz: fast transforms along the rows, else rows times the transposed
+  // dense spectral operator
+  if (g.sz.nrad) {
+    if (eles::launch_sder(g, true, ubar, feat + 2 * n, (long)(3 * n), stream) != hipSuccess) return ELES_EHIP;
+  } else if (eles::launch_dz(g, ubar, feat + 2 * n, (long)(3 * n), stream) != hipSuccess) {
+    return ELES_EHIP;
+  }
   if (eles::launch_walldist(f->v.y64, nx, ny, nz, feat + 9 * n, stream) != hipSuccess) return ELES_EHIP;
   return ELES_OK;
 }

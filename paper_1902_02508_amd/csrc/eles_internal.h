@@ -140,6 +140,32 @@ hipError_t launch_stats(const double *part, double *stats, int ny, int nparts,
                         double inv_count, hipStream_t s);
 
 // ---- closure features: gradient operators of the grid (filter state)
+
+// Spectral derivative along a periodic axis by fast transforms (k_sder.hip):
+// the radices of n (16, 8, 4, 2, 3, 5; nrad = 0 when n has another prime
+// factor or the lines do not fit a block, and the dense operator is used),
+// P complex lines per block, division magics ceil(2^32 / d) of the pass
+// geometry, the factor 2 pi / (L n) and the table exp(-2 pi i m / n).
+constexpr int kSderMaxPass = 8;
+struct SderAxis {
+  int n, P, lp, E, T, nrad;      // E complex values per thread, T threads per block
+  int rad[kSderMaxPass];
+  uint32_t mnr[kSderMaxPass];    // of n / rad[s]
+  uint32_t mns[kSderMaxPass];    // of the forward pass's Ns
+  uint32_t imns[kSderMaxPass];   // of the inverse pass's Ns (radices reversed)
+  float cfac;
+  float2 *tw;                    // [n] in the filter state
+};
+struct SderArgs {
+  SderAxis ax;
+  const float *in;
+  float *out;
+  long in_fs, out_fs;
+  int nx, ny, nz, zaxis;
+};
+bool sder_plan(int n, double length, bool zaxis, SderAxis *a);
+size_t sder_lds_bytes(const SderAxis &a);
+
 struct GradView {
   int nx, ny, nz, mpx, kpx, mpz, kpz, mpy, kpy;
   double lx, lz;
@@ -150,6 +176,7 @@ struct GradView {
   float *dy32[2];              // y derivative of even / odd fields [mpy][kpy]
   uint16_t *dyhi[2], *dylo[2];
   int *dyband;                 // [mpy][2]
+  SderAxis sx, sz;             // fast spectral derivatives along x and z
 };
 hipError_t launch_build_grad_ops(const GradView &v, const double *y64, hipStream_t s);
 hipError_t launch_dz(const GradView &v, const float *ubar, float *out, long out_fstride, hipStream_t s);
@@ -157,6 +184,12 @@ hipError_t launch_dz(const GradView &v, const float *ubar, float *out, long out_
 // out + f * out_fstride; needs ny >= 3
 hipError_t launch_ddy(const GradView &v, const float *ubar, float *out, long out_fstride, unsigned pmask,
                       hipStream_t s);
+// tables and LDS limit of the fast spectral derivatives
+hipError_t sder_setup(const SderAxis &a, hipStream_t s);
+// d/dx (zaxis false) or d/dz of the three fields at ubar into
+// out + f * out_fstride by fast transforms; needs the axis's nrad > 0
+hipError_t launch_sder(const GradView &v, bool zaxis, const float *ubar, float *out, long out_fstride,
+                       hipStream_t s);
 hipError_t launch_walldist(const double *y64, int nx, int ny, int nz, float *out, hipStream_t s);
 
 // ---- the perceptron

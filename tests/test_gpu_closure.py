@@ -42,22 +42,76 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
 
 
-@pytest.mark.parametrize("base,over", [("tiny", {}), ("dns192", dict(nx=40, nz=36, ny=33)),
-                                       ("tiny", dict(nx=15, nz=21, ny=17, ykind="tanh", stretch=2.0)),
-                                       # y segments of 2, 2, 1 rows and of one row (the wall rows
-                                       # alone in theirs); two z blocks, the second partial
-                                       ("tiny", dict(nx=8, nz=70, ny=5)),
-                                       ("tiny", dict(nx=12, nz=8, ny=4))])
-def test_features_match_oracle(E, base, over):
+def _feature_input(cfg, seed, filtered):
+    """The velocity the features are taken of: the FP64 filtered field of
+    the oracle (rounded to FP32), or the unfiltered generator field for the
+    long lines the oracle's dense filter would take minutes on."""
+    y, u = synth.make_snapshot(cfg, seed)
+    if filtered:
+        u, _ = R.sgs_stress(u, R.Operators.from_config(cfg))
+    return y, np.asarray(u, dtype=np.float32)
+
+
+_PI = math.pi
+
+
+@pytest.mark.parametrize("base,over,filtered", [
+    ("tiny", {}, True),
+    ("dns192", dict(nx=40, nz=36, ny=33), True),
+    ("tiny", dict(nx=15, nz=21, ny=17, ykind="tanh", stretch=2.0), True),
+    # y segments of 2, 2, 1 rows and of one row (the wall rows alone in
+    # theirs); two z blocks, the second partial
+    ("tiny", dict(nx=8, nz=70, ny=5), True),
+    ("tiny", dict(nx=12, nz=8, ny=4), True),
+    # transform radices 16, 4, 3 (192), 2, 3, 5 (30) and 16, 2 (32); lines
+    # of one and two nodes
+    ("dns192", dict(ny=9), True),
+    ("tiny", dict(nx=30, nz=2, ny=7), True),
+    ("tiny", dict(nx=1, nz=32, ny=5), True),
+    # the production line lengths (1024 along x, 768 along z), and lines of
+    # 4096 and 8192 nodes (two and one complex line per block)
+    ("dns192", dict(nx=1024, ny=5, nz=768, delta_x=4 * _PI / 256, delta_z=2 * _PI / 192), False),
+    ("dns192", dict(nx=4096, ny=3, nz=10, delta_x=4 * _PI / 1024, delta_z=2 * _PI / 4), False),
+    ("dns192", dict(nx=6, ny=3, nz=8192, delta_x=4 * _PI / 4, delta_z=2 * _PI / 2048), False)])
+def test_features_match_oracle(E, base, over, filtered):
+    """Every feature against the oracle's FP64 gradient of the same FP32
+    velocity, relative L2. Where the line length factors into 2, 3 and 5
+    the x and z derivatives are FP32 fast transforms, whose normwise
+    rounding error is of order 2^-24 log2(n) in the coefficients; the
+    derivative scales the high modes by up to k_max = pi n / L, so the bound
+    is max(1e-5, 2^-24 log2(n) (1 + k_max |u| / |du|)). The dense BF16x3
+    operator (21 and 70 nodes) is held to 1e-4, the y differences to 1e-5."""
     cfg = synth.config(base, **over)
-    y, u = synth.make_snapshot(cfg, 2)
+    y, ub = _feature_input(cfg, 2, filtered)
     f = E.Filter.from_config(cfg)
-    ub, _, _ = f.sgs_stress(_dev(u), stats=False)
-    feat = _host(E.features(f, ub))
-    ref = C.features(_host(ub), y, cfg.lx, cfg.lz)
+    feat = _host(E.features(f, _dev(ub)))
+    ref = C.features(ub.astype(np.float64), y, cfg.lx, cfg.lz)
+
+    def smooth(n):
+        while n > 1 and any(n % r == 0 for r in (2, 3, 5)):
+            n //= next(r for r in (2, 3, 5) if n % r == 0)
+        return n == 1
+
+    def lim(k):
+        if k == 9:
+            return 1e-7
+        if np.linalg.norm(ref[k]) == 0:     # lines of one or two nodes: exactly zero
+            return 1e-30
+        i, d = divmod(k, 3)
+        if d == 1:
+            return 1e-5
+        n, length = (cfg.nx, cfg.lx) if d == 0 else (cfg.nz, cfg.lz)
+        if n < 2 or not smooth(n):
+            return 1e-4
+        kappa = math.pi * n / length * np.linalg.norm(ub[i]) / np.linalg.norm(ref[k])
+        return max(1e-5, 2.0 ** -24 * math.log2(n) * (1.0 + kappa))
+    errs = []
     for k in range(10):
         err = _rel(feat[k], ref[k]) if np.linalg.norm(ref[k]) > 0 else np.abs(feat[k]).max()
-        assert err < 1e-4, (k, err)
+        errs.append(err)
+        assert err <= lim(k), (k, err, lim(k), errs)
+    print(f"features {cfg.nx}x{cfg.ny}x{cfg.nz}: " + " ".join(f"{e:.1e} ({lim(k):.0e})" for k, e in enumerate(errs)),
+          flush=True)
 
 
 def test_sampler_bit_exact(E):
@@ -104,15 +158,15 @@ def test_inference_matches_oracle(E, physics):
     raw features and adds no BF16 rounding."""
     cfg = synth.config("dns192", nx=32, nz=32, ny=33)
     y, u = synth.make_snapshot(cfg, 4)
+    ub64, tau64 = R.sgs_stress(u, R.Operators.from_config(cfg))
+    ub = ub64.astype(np.float32)
+    feat = C.features(ub.astype(np.float64), y, cfg.lx, cfg.lz)
+    norms = _norms(feat, tau64)
     f = E.Filter.from_config(cfg)
-    ub, tau, _ = f.sgs_stress(_dev(u), stats=False)
-    feat = _host(E.features(f, ub))
-    taun = _host(tau)
-    norms = _norms(feat, taun)
     coef = C.widths_coef(cfg.delta_x, cfg.delta_y, cfg.delta_z) if physics else (0.0, 0.0, 0.0)
     theta = C.init_params(11) * 2.0
     cl = E.Closure(theta, norms, gm_coef=coef if physics else None)
-    pred, st = cl.infer(f, ub)
+    pred, st = cl.infer(f, _dev(ub))
     pred = _host(pred)
     xs = ((feat.reshape(10, -1).T - norms[:10]) / norms[10:20])
     th32 = theta.astype(np.float32).astype(np.float64)
@@ -131,16 +185,17 @@ def test_inference_matches_oracle(E, physics):
 
 
 def _dataset(E, n_snap=2):
+    """Training data from the oracle: features of the FP64 filtered field
+    (rounded to FP32) and its exact stress, in FP32 on the device."""
     cfg = synth.config("dns192", nx=32, nz=32, ny=33)
+    ops = R.Operators.from_config(cfg)
     feats, taus = [], []
-    f = E.Filter.from_config(cfg)
     for s in range(n_snap):
         y, u = synth.make_snapshot(cfg, 100 + s)
-        ub, tau, _ = f.sgs_stress(_dev(u), stats=False)
-        feats.append(E.features(f, ub).clone())
-        taus.append(tau.clone())
-    import torch
-    return cfg, torch.stack(feats), torch.stack(taus)
+        ub, tau = R.sgs_stress(u, ops)
+        feats.append(C.features(ub.astype(np.float32).astype(np.float64), y, cfg.lx, cfg.lz))
+        taus.append(tau)
+    return cfg, _dev(np.stack(feats)), _dev(np.stack(taus))
 
 
 @pytest.mark.parametrize("physics", [False, True])
