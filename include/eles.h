@@ -339,14 +339,17 @@ void les_destroy(eles_les h);
  * 64 -> 6 with GELU hidden layers and a linear output. GELU(x) = x Phi(x),
  * Phi the standard normal CDF; the kernels evaluate it as max(x, 0) -
  * h(min(|x|, 4)) with h a degree-7 polynomial fitted to s Phi(-s), within
- * 2.4e-4 of x Phi(x) (derivative within 5e-3), below the BF16 resolution
- * of the activations. Its
+ * 2.4e-4 of x Phi(x) in exact arithmetic (training: in s, FP32, derivative
+ * within 5e-3; inference: in s/2 - 1, packed FP16, within 1.3e-3 as
+ * rounded). Its
  * inputs at every grid point are the nine components d ubar_i / d x_k
  * (i, k = 1..3, row-major) of the filtered velocity gradient and the wall
  * distance 1 - |y|; its outputs are tau_11, tau_12, tau_13, tau_22, tau_23,
  * tau_33. Inputs and outputs are standardised with training-set means and
- * standard deviations. Weights and activations are BF16 on the matrix
- * cores with FP32 accumulation; master weights and Adam moments are FP32.
+ * standard deviations. Training runs BF16 weights and activations on the
+ * matrix cores with FP32 accumulation, master weights and Adam moments in
+ * FP32; inference runs FP16 weights (rounded from the FP32 masters) and
+ * activations with FP32 accumulation.
  * Parameters are packed W1 (64x10, row-major), b1, W2 (64x64), b2, W3, b3,
  * W4 (6x64), b4: ELES_CLOSURE_NPARAM floats.
  * ====================================================================== */

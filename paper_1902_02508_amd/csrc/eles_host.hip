@@ -714,7 +714,10 @@ size_t infer_ws(const eles_filter_s *f, bool exact, InferWs *w) {
   InferWs o;
   o.off_sgs = off_sgs;
   o.off_part = r0;
-  o.off_stats = o.off_part + up256((size_t)eles::plane_mean_parts(6, f->d.ny) * 8);
+  // the row sums of the prediction, or the plane-mean partials of the
+  // exact stress after a fallback
+  const size_t rows = (size_t)6 * f->d.nx * f->d.ny;
+  o.off_stats = o.off_part + up256(std::max(rows, (size_t)eles::plane_mean_parts(6, f->d.ny)) * 8);
   o.off_flag = o.off_stats + up256((size_t)6 * f->d.ny * 8);
   if (w) *w = o;
   return o.off_flag + 256;
@@ -865,10 +868,9 @@ int32_t dense_dx(eles_filter f, const float *ubar, float *feat, hipStream_t stre
   return eles::launch_y(ya, false, ELES_YGEMM_BF16X3, stream) == hipSuccess ? ELES_OK : ELES_EHIP;
 }
 
-int32_t closure_features(eles_filter f, const float *ubar, float *feat, hipStream_t stream) {
-  if (!f || !ubar || !feat || !aligned16(ubar) || !aligned16(feat)) return ELES_EINVAL;
+// features 0..8 (the velocity gradient) and, with walldist, feature 9
+int32_t gradient_features(eles_filter f, const float *ubar, float *feat, bool walldist, hipStream_t stream) {
   const size_t n = f->npts;
-  if (overlap(ubar, 3 * n * 4, feat, 10 * n * 4)) return ELES_EINVAL;
   const int nx = f->d.nx, ny = f->d.ny, nz = f->d.nz;
   const eles::GradView &g = f->gv;
   // d/dx: fast transforms along x where nx factors into 2, 3 and 5, else
@@ -910,8 +912,16 @@ int32_t closure_features(eles_filter f, const float *ubar, float *feat, hipStrea
   } else if (eles::launch_dz(g, ubar, feat + 2 * n, (long)(3 * n), stream) != hipSuccess) {
     return ELES_EHIP;
   }
-  if (eles::launch_walldist(f->v.y64, nx, ny, nz, feat + 9 * n, stream) != hipSuccess) return ELES_EHIP;
+  if (walldist && eles::launch_walldist(f->v.y64, nx, ny, nz, feat + 9 * n, stream) != hipSuccess)
+    return ELES_EHIP;
   return ELES_OK;
+}
+
+int32_t closure_features(eles_filter f, const float *ubar, float *feat, hipStream_t stream) {
+  if (!f || !ubar || !feat || !aligned16(ubar) || !aligned16(feat)) return ELES_EINVAL;
+  const size_t n = f->npts;
+  if (overlap(ubar, 3 * n * 4, feat, 10 * n * 4)) return ELES_EINVAL;
+  return gradient_features(f, ubar, feat, true, stream);
 }
 
 size_t closure_moments_workspace_bytes(int32_t nchan) {
@@ -988,12 +998,16 @@ int32_t closure_infer(eles_closure c, eles_filter f, const float *ubar, float *t
   char *base = (char *)ws;
   float *feat = (float *)base;
   double *part = (double *)(base + w.off_part);
-  int32_t st = closure_features(f, ubar, feat, stream);
+  // the network computes the wall distance itself
+  int32_t st = gradient_features(f, ubar, feat, false, stream);
   if (st != ELES_OK) return st;
-  if (eles::launch_infer(c->c, feat, (long)n, tau_pred, stream) != hipSuccess) return ELES_EHIP;
-  // plane sums: the caller's stats, or (for the check alone) the workspace's
+  // plane means: the caller's stats, or (for the check alone) the
+  // workspace's, from the network kernel's row sums
   double *sums = stats ? stats : (checked ? (double *)(base + w.off_stats) : nullptr);
-  if (sums && eles::launch_plane_mean(tau_pred, 6, f->d.nx, f->d.ny, f->d.nz, part, sums, stream) != hipSuccess)
+  if (eles::launch_infer(c->c, feat, f->d.nx, f->d.ny, f->d.nz, f->v.y64, tau_pred, sums ? part : nullptr,
+                         stream) != hipSuccess)
+    return ELES_EHIP;
+  if (sums && eles::launch_row_means(part, 6, f->d.nx, f->d.ny, f->d.nz, sums, stream) != hipSuccess)
     return ELES_EHIP;
   if (!checked) return ELES_OK;
   // a NaN or infinity anywhere in tau_pred makes its plane's FP64 sum

@@ -236,12 +236,18 @@ struct AdamArgs {
 };
 hipError_t launch_sample(uint64_t seed, long step, int batch, uint64_t count, int64_t *out, hipStream_t s);
 hipError_t launch_shadows(const ClosureView &c, hipStream_t s);
-hipError_t launch_infer(const ClosureView &c, const float *feat, long npts, float *out, hipStream_t s);
+// the closure on features 0..8 of feat [10][nx ny nz] (the wall distance is
+// taken from y64) into out [6][...]; with rows, the FP64 sums of each
+// output over every (x, y) row into rows [6][nx ny]
+hipError_t launch_infer(const ClosureView &c, const float *feat, int nx, int ny, int nz, const double *y64,
+                        float *out, double *rows, hipStream_t s);
 hipError_t launch_moments(const float *data, int nchan, int nsnap, long npts, double *part, int nchunks,
                           double *out, hipStream_t s);
 // Plane means and the non-finite test (k_check.hip, built with IEEE
 // semantics). part: FP64 scratch of plane_mean_parts(nq, ny) values.
 inline long plane_mean_parts(int nq, int ny) { return (long)nq * ny * 16; }
+// plane means out [nq][ny] from the row sums of launch_infer
+hipError_t launch_row_means(const double *rows, int nq, int nx, int ny, int nz, double *out, hipStream_t s);
 hipError_t launch_plane_mean(const float *f, int nq, int nx, int ny, int nz, double *part, double *out,
                              hipStream_t s);
 // *flag (device) = 1 if any of v[0..n) (device FP64) is NaN or infinite.

@@ -50,6 +50,24 @@ __global__ void __launch_bounds__(256) k_plane_final(const double *part, int n, 
   out[i] = s * inv;
 }
 
+// <f_q>(y_j) from the FP64 sums of each (x, y) row, rows[q][x ny + j]:
+// one block per (j, q), thread t adding x = t, t + 256, ... in order, then
+// a fixed tree over the threads
+__global__ void __launch_bounds__(256) k_row_means(const double *rows, int nx, int ny, double inv, double *out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x, q = blockIdx.y;
+  const double *r = rows + (long)q * nx * ny + j;
+  double s = 0.0;
+  for (int x = threadIdx.x; x < nx; x += 256) s += r[(long)x * ny];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[q * ny + j] = red[0] * inv;
+}
+
 // flag = 1 if any of v[0..n) has an all-ones exponent (NaN or infinity),
 // else 0; one block.
 __global__ void __launch_bounds__(256) k_nonfinite(const double *v, int n, int *flag) {
@@ -70,6 +88,11 @@ hipError_t launch_plane_mean(const float *f, int nq, int nx, int ny, int nz, dou
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_plane_final<<<(nq * ny + 255) / 256, 256, 0, s>>>(part, nq * ny, 1.0 / ((double)nx * nz), out);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_means(const double *rows, int nq, int nx, int ny, int nz, double *out, hipStream_t s) {
+  k_row_means<<<dim3(ny, nq), 256, 0, s>>>(rows, nx, ny, 1.0 / ((double)nx * nz), out);
   return hipGetLastError();
 }
 

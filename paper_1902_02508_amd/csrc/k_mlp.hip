@@ -1,8 +1,9 @@
 // The learned closure: a 10-64-64-64-6 perceptron with GELU hidden layers
 // that maps the filtered velocity gradient and the wall distance to the six
-// components of the exact stress. Weights and activations are BF16 on the
-// matrix cores with FP32 accumulation; master weights, Adam moments and the
-// loss are FP32 / FP64.
+// components of the exact stress. Training runs BF16 weights and
+// activations on the matrix cores with FP32 accumulation; master weights,
+// Adam moments and the loss are FP32 / FP64. Inference runs FP16 weights
+// and activations (the GELU in packed FP16).
 //
 // Training runs layer by layer over a minibatch drawn with SplitMix64
 // (counter-based, so a step's batch depends only on the seed and the step
@@ -11,7 +12,8 @@
 // batch as contiguous K, and split-K partials are summed in a fixed order by
 // the Adam kernel. Inference runs all four layers of a 16-point tile inside
 // one wave, weights held in registers, activations through a 2 KB LDS
-// transpose.
+// transpose, and adds up each (x, y) row of its outputs for the plane
+// means.
 #include "k_gemm.h"
 
 namespace eles {
@@ -19,6 +21,9 @@ namespace {
 
 constexpr int H = kMlpHidden;
 constexpr int K1 = kMlpInPad;
+// word 3 of a raw buffer descriptor on gfx9-family parts (32-bit data
+// format, no swizzle)
+constexpr int kBufWord3 = 0x00020000;
 
 // GELU(x) = x Phi(x) evaluated without transcendentals: max(x, 0) - h(s),
 // s = min(|x|, 4), h(s) = sum_k c_k s^k (k = 1..7) fitted to s Phi(-s) with
@@ -332,7 +337,7 @@ __global__ void __launch_bounds__(256) k_shadows(ClosureView c) {
 
 // -------------------------------------------------------------- inference
 
-constexpr int kInferWavesPerCu = 12;
+constexpr int kInferWavesPerCu = 16;
 
 
 __device__ inline void wave_sync() {
@@ -341,20 +346,84 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// All four layers of 16-point tiles. Each wave keeps its A fragments of W1,
-// W2 and W4 in registers for the whole run (W3 is read from LDS) and loops
-// over tiles, fetching the next tile's features while the current one is
-// computed; a tile's activations go through a per-wave 16 x 64 BF16 LDS
-// transpose between layers. Each layer's products start from its bias (the
-// accumulator's initial value), so the epilogue adds nothing.
-__global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__restrict__ feat, long npts,
-                                               float *__restrict__ out) {
-  // LDS rows of W3 and of the activation transposes are HP = H + 8 BF16
+// ---- inference arithmetic: FP16 weights and activations on the matrix
+// cores (v_mfma_f32_16x16x32_f16, FP32 accumulation) and the GELU in packed
+// FP16, two values per instruction. The GELU is the same max(x, 0) - h(s),
+// s = min(|x|, 4), with h a degree-7 polynomial in u = s/2 - 1 fitted to
+// s Phi(-s) with FP16 coefficients (within 2.4e-4 of x Phi(x) in exact
+// arithmetic): Horner in u keeps the intermediates below one in magnitude,
+// where the powers of s would cancel from tens and lose the FP16 digits.
+typedef _Float16 gh2 __attribute__((ext_vector_type(2)));
+typedef _Float16 gh8 __attribute__((ext_vector_type(8)));
+
+__device__ inline gh2 gelu16_h(gh2 u) {
+  gh2 h = (gh2)(_Float16)-0.0816650390625f;
+  h = h * u + (_Float16)0.05841064453125f;
+  h = h * u + (_Float16)0.239013671875f;
+  h = h * u + (_Float16)-0.32568359375f;
+  h = h * u + (_Float16)0.0142974853515625f;
+  h = h * u + (_Float16)0.2218017578125f;
+  h = h * u + (_Float16)-0.171630859375f;
+  h = h * u + (_Float16)0.04534912109375f;
+  return h;
+}
+
+// GELU of two FP32 pre-activations, returned as two FP16 (low, high)
+__device__ inline uint32_t gelu16x2(float a, float b) {
+  const gh2 x = __builtin_convertvector(gf2{a, b}, gh2);
+  const gh2 s = __builtin_elementwise_min(__builtin_elementwise_abs(x), (gh2){(_Float16)4.0f, (_Float16)4.0f});
+  const gh2 h = gelu16_h(s * (_Float16)0.5f - (_Float16)1.0f);
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, (gh2){(_Float16)0.0f, (_Float16)0.0f}) - h);
+}
+
+__device__ inline uint32_t h16x2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(gf2{a, b}, gh2));
+}
+
+__device__ inline gf4 h_mma(gus8 a, gus8 b, gf4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(gh8, a), __builtin_bit_cast(gh8, b), c, 0, 0, 0);
+}
+
+// eight FP32 weights (zero past n) as an FP16 A fragment
+__device__ inline gus8 w16(const float *w, int n) {
+  uint32_t q[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) q[e] = h16x2(2 * e < n ? w[2 * e] : 0.0f, 2 * e + 1 < n ? w[2 * e + 1] : 0.0f);
+  return __builtin_bit_cast(gus8, q);
+}
+
+struct InferArgs {
+  ClosureView c;
+  const float *feat;   // features 0..8 of [10][npts]; the wall distance is computed
+  long npts;
+  int nx, ny, nz;
+  const double *y64;   // the grid's y nodes
+  float *out;          // [6][npts]
+  double *rows;        // [6][nx ny] sums of each output over a (x, y) row, or null
+};
+
+// All four layers of 16-point tiles. Each wave walks whole (x, y) rows of
+// the grid (row = wave, wave + nwaves, ...), a row as ceil(nz / 16) tiles
+// of 16 consecutive z, fetching the next tile's features while the current
+// one is computed. It keeps its A fragments of W1 and W4 in registers (W2
+// and W3 in LDS, which leaves 128 registers: four waves per SIMD),
+// converted from the FP32 master weights; a tile's
+// activations go through a per-wave 16 x 64 FP16 LDS transpose between
+// layers; each layer's products start from its bias. The wall-distance
+// feature 1 - |y| is the row's (the same FP32 value the feature kernel
+// stores). With rows given, every lane adds its outputs of the row in FP64
+// in tile order and the sixteen points of a tile are then added across
+// lanes in a fixed butterfly: the (x, y) row sums, deterministic, which
+// the plane means reduce over x.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_infer(InferArgs a) {
+  const ClosureView &c = a.c;
+  // LDS rows of W2, W3 and of the activation transposes are HP = H + 8 halves
   // (36 words): the sixteen lanes of a lane group, one row each, then fall
   // on disjoint banks (a 32-word stride puts them all on the same ones)
   constexpr int HP = H + 8;
   __shared__ __attribute__((aligned(16))) float sb[3 * H + 16];
   __shared__ __attribute__((aligned(16))) uint16_t sw3[H * HP];
+  __shared__ __attribute__((aligned(16))) uint16_t sw2[H * HP];
   __shared__ __attribute__((aligned(16))) uint16_t sh[4][16 * HP];
   for (int i = threadIdx.x; i < 3 * H + 16; i += 256) {
     float b = 0.0f;
@@ -364,55 +433,79 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
     else if (i - 3 * H < kMlpOut) b = c.theta[kMlpOffB4 + i - 3 * H];
     sb[i] = b;
   }
-  for (int i = threadIdx.x; i < H * H / 8; i += 256)
-    *reinterpret_cast<gus8 *>(sw3 + (i / (H / 8)) * HP + 8 * (i % (H / 8))) =
-        reinterpret_cast<const gus8 *>(c.w3)[i];
+  const float *W1 = c.theta, *W2 = c.theta + kMlpOffB1 + H, *W3 = c.theta + kMlpOffB2 + H,
+              *W4 = c.theta + kMlpOffB3 + H;
+  for (int i = threadIdx.x; i < H * H / 8; i += 256) {
+    const int n = i / (H / 8), k = 8 * (i % (H / 8));
+    *reinterpret_cast<gus8 *>(sw3 + n * HP + k) = w16(W3 + n * H + k, 8);
+    *reinterpret_cast<gus8 *>(sw2 + n * HP + k) = w16(W2 + n * H + k, 8);
+  }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, grp = lane >> 4;
   uint16_t *hs = sh[wave];
-  gus8 a1[4], a2[4][2], a4[2];
+  gus8 a1[4], a4[2];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    a1[t] = *reinterpret_cast<const gus8 *>(c.w1 + (16 * t + col) * K1 + 8 * grp);
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-      a2[t][s] = *reinterpret_cast<const gus8 *>(c.w2 + (16 * t + col) * H + 32 * s + 8 * grp);
+    a1[t] = w16(W1 + (16 * t + col) * kMlpIn + 8 * grp, grp == 0 ? 8 : (grp == 1 ? kMlpIn - 8 : 0));
+
   }
 #pragma unroll
-  for (int s = 0; s < 2; ++s) a4[s] = *reinterpret_cast<const gus8 *>(c.w4 + col * H + 32 * s + 8 * grp);
-  // lane (point col, group grp) carries features 8 grp .. 8 grp + 7
+  for (int s = 0; s < 2; ++s) a4[s] = w16(W4 + (col < kMlpOut ? col : 0) * H + 32 * s + 8 * grp, col < kMlpOut ? 8 : 0);
+  // lane (point col, group grp) carries features 8 grp .. 8 grp + 7; of
+  // group 1, feature 8 is loaded and feature 9 is the wall distance
   const int nf = grp == 0 ? 8 : (grp == 1 ? kMlpIn - 8 : 0);
+  const int nload = grp == 0 ? 8 : (grp == 1 ? 1 : 0);
   float fsc[8], fsh[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     fsc[e] = e < nf ? c.fsc[8 * grp + e] : 0.0f;
     fsh[e] = e < nf ? c.fsh[8 * grp + e] : 0.0f;
   }
-  const long ntile = (npts + 15) / 16;
-  const long stride = (long)gridDim.x * 4;
-  float fv[8];
-  auto fetch = [&](long tile) {
-    const long p = tile * 16 + col;
-    const bool ok = tile < ntile && p < npts;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) fv[e] = (ok && e < nf) ? feat[(long)(8 * grp + e) * npts + p] : 0.0f;
+  // The row cursor is wave-uniform (scalar registers): each tile reads
+  // and writes through buffer descriptors of its row's piece of every
+  // plane (nz floats), so points past nz read zeros and drop their stores,
+  // and a lane outside a load's or store's lane group gets an offset past
+  // the range.
+  const int nrows = a.nx * a.ny;
+  const int ntz = (a.nz + 15) / 16;
+  const int nw = (int)gridDim.x * 4;
+  const long npts = a.npts;
+  const unsigned nbytes = (unsigned)a.nz * 4u, kOut = 0x80000000u;
+  auto plane = [&](const float *base, int q, int r) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(base + (long)q * npts + (long)r * a.nz), 0, (int)nbytes,
+                                             kBufWord3);
   };
-  long tile = (long)blockIdx.x * 4 + wave;
-  fetch(tile);
-  for (; tile < ntile; tile += stride) {
-    const long p = tile * 16 + col;
-    const bool pok = p < npts;
-    gus8 xb;
+  int row = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wave);
+  int zb = 0;
+  float fv[8];
+  auto fetch = [&](int r, int b) {
+    const unsigned off = (unsigned)(16 * b + col) * 4u;
+    const unsigned o0 = grp == 0 && r < nrows ? off : kOut, o1 = grp == 1 && r < nrows ? off : kOut;
+    const int rr = __builtin_amdgcn_readfirstlane(r < nrows ? r : 0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      fv[e] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(plane(a.feat, e, rr), o0, 0, 0));
+    const float f8 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(plane(a.feat, 8, rr), o1, 0, 0));
+    fv[0] = grp == 1 ? f8 : fv[0];
+  };
+  fetch(row, zb);
+  double rs[4] = {0.0, 0.0, 0.0, 0.0};
+  float wall = row < nrows ? (float)(1.0 - fabs(a.y64[row % a.ny])) : 0.0f;
+  while (row < nrows) {
+    const int z = 16 * zb + col;
+    const bool pok = z < a.nz;
+    const unsigned zoff = (unsigned)z * 4u;
+    if (grp == 1) fv[1] = wall;
+    uint32_t xw[4];
     {
       float xs[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) xs[e] = e < nf ? fv[e] * fsc[e] + fsh[e] : 0.0f;
-      uint32_t w[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) w[e] = g_bf16x2(xs[2 * e], xs[2 * e + 1]);
-      xb = __builtin_bit_cast(gus8, w);
+      for (int e = 0; e < 4; ++e) xw[e] = h16x2(xs[2 * e], xs[2 * e + 1]);
     }
+    const gus8 xb = __builtin_bit_cast(gus8, xw);
     // gradient-model term of this lane's outputs 4 grp + r, from the raw
     // features of the current tile (lanes of group 0 hold features 0..7,
     // of group 1 features 8, 9; the others are exchanged)
@@ -434,24 +527,24 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
 #pragma unroll
       for (int r = 0; r < 4; ++r) gmr[r] = grp == 0 ? G[r] : (r < 2 ? G[4 + r] : 0.0f);
     }
-    fetch(tile + stride);
-    // the four bias values of accumulator t of a layer whose biases start
-    // at sb + base: rows 16 t + 4 grp .. + 3
+    // advance the cursor and request the next tile's features
+    const int crow = __builtin_amdgcn_readfirstlane(row);
+    if (++zb == ntz) {
+      zb = 0;
+      row = __builtin_amdgcn_readfirstlane(row + nw);
+    }
+    fetch(row, zb);
     auto bias = [&](int base, int t) { return *reinterpret_cast<const gf4 *>(sb + base + 16 * t + 4 * grp); };
     gf4 acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = g_mma(a1[t], xb, bias(0, t));
+    for (int t = 0; t < 4; ++t) acc[t] = h_mma(a1[t], xb, bias(0, t));
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       // GELU of layer l, transposed through LDS into the next B operand
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        float hv[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) hv[r] = gelu(acc[t][r]);
+      for (int t = 0; t < 4; ++t)
         *reinterpret_cast<uint2 *>(hs + col * HP + 16 * t + 4 * grp) =
-            make_uint2(g_bf16x2(hv[0], hv[1]), g_bf16x2(hv[2], hv[3]));
-      }
+            make_uint2(gelu16x2(acc[t][0], acc[t][1]), gelu16x2(acc[t][2], acc[t][3]));
       wave_sync();
       gus8 bk[2];
 #pragma unroll
@@ -463,21 +556,47 @@ __global__ void __launch_bounds__(256) k_infer(ClosureView c, const float *__res
           acc[t] = bias((l + 1) * H, t);
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
-            const gus8 aw = l == 0 ? a2[t][s]
+            const gus8 aw = l == 0 ? *reinterpret_cast<const gus8 *>(sw2 + (16 * t + col) * HP + 32 * s + 8 * grp)
                                    : *reinterpret_cast<const gus8 *>(sw3 + (16 * t + col) * HP + 32 * s + 8 * grp);
-            acc[t] = g_mma(aw, bk[s], acc[t]);
+            acc[t] = h_mma(aw, bk[s], acc[t]);
           }
         }
       } else {
         gf4 y = bias(3 * H, 0);   // output biases, zero past the sixth row
 #pragma unroll
-        for (int s = 0; s < 2; ++s) y = g_mma(a4[s], bk[s], y);
+        for (int s = 0; s < 2; ++s) y = h_mma(a4[s], bk[s], y);
+        // lane group 0 holds outputs 0..3, group 1 outputs 4, 5
+        const unsigned s0 = grp == 0 ? zoff : kOut, s1 = grp == 1 ? zoff : kOut;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int o = 4 * grp + r;
-          if (o < kMlpOut && pok) out[(long)o * npts + p] = y[r] * c.isc[o] + c.ish[o] + gmr[r];
+          const float v = y[r] * c.isc[o < kMlpOut ? o : 0] + c.ish[o < kMlpOut ? o : 0] + gmr[r];
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), plane(a.out, r, crow), s0, 0, 0);
+          if (r < 2)
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), plane(a.out, 4 + r, crow), s1, 0, 0);
+          rs[r] += (o < kMlpOut && pok) ? (double)v : 0.0;
         }
       }
+    }
+    if (row != crow) {
+      // the row is done: its sums across the sixteen points, then reset
+      if (a.rows) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+          for (int m = 1; m < 16; m <<= 1) rs[r] += __shfl_xor(rs[r], m, 64);
+        }
+        if (col == 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int o = 4 * grp + r;
+            if (o < kMlpOut) a.rows[(long)o * nrows + crow] = rs[r];
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rs[r] = 0.0;
+      if (row < nrows) wall = (float)(1.0 - fabs(a.y64[row % a.ny]));
     }
   }
 }
@@ -532,12 +651,14 @@ hipError_t launch_shadows(const ClosureView &c, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_infer(const ClosureView &c, const float *feat, long npts, float *out, hipStream_t s) {
-  const long tiles = (npts + 15) / 16;
-  long blocks = (tiles + 3) / 4;
-  const long cap = 256L * kInferWavesPerCu / 4;   // every wave keeps its weights for many tiles
+hipError_t launch_infer(const ClosureView &c, const float *feat, int nx, int ny, int nz, const double *y64,
+                        float *out, double *rows, hipStream_t s) {
+  const long nrows = (long)nx * ny;
+  long blocks = (nrows + 3) / 4;
+  const long cap = 256L * kInferWavesPerCu / 4;   // every wave keeps its weights for many rows
   if (blocks > cap) blocks = cap;
-  k_infer<<<(unsigned)blocks, 256, 0, s>>>(c, feat, npts, out);
+  InferArgs a{c, feat, nrows * nz, nx, ny, nz, y64, out, rows};
+  k_infer<<<(unsigned)blocks, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

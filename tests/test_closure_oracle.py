@@ -104,6 +104,26 @@ def test_kernel_gelu_approximation_bound():
     assert np.max(np.abs(K.gelu_grad(x) - C.gelu_grad(x))) < 5e-3
 
 
+def test_kernel_gelu16_approximation_bound():
+    """Inference evaluates the GELU in packed FP16: max(x, 0) - h(min(|x|,
+    4)) with h a degree-7 polynomial in u = s/2 - 1 whose coefficients are
+    FP16 numbers. In exact arithmetic it is within 2.4e-4 of x Phi(x); as
+    the kernel rounds it (FP16 input, fused FP16 Horner steps, FP16 result)
+    within 1.3e-3 absolute over |x| <= 10, and within 7.5e-4 for |x| <= 2,
+    where the activations are small. The GPU parity tolerances carry the
+    effect on the network."""
+    import kernel_gelu as K
+    e = K.coefficients16()
+    assert all(float(np.float16(v)) == v for v in e)
+    x = np.linspace(-30, 30, 600001)
+    assert np.max(np.abs(K.gelu16(x) - C.gelu(x))) < 2.4e-4
+    x = np.linspace(-10, 10, 400001)
+    x16 = x.astype(np.float16).astype(np.float64)
+    err = np.abs(K.gelu16_rounded(x16) - C.gelu(x16))
+    assert err.max() < 1.3e-3
+    assert err[np.abs(x16) <= 2].max() < 7.5e-4
+
+
 def test_backprop_matches_finite_differences():
     rng = np.random.default_rng(0)
     layers = (10, 8, 7, 6, 6)
