@@ -124,6 +124,22 @@ def test_kernel_gelu16_approximation_bound():
     assert err[np.abs(x16) <= 2].max() < 7.5e-4
 
 
+def test_fp16_inference_rounding():
+    """The inference kernel's roundings (FP16 weights, inputs and
+    activations, the FP16 GELU) keep the network within 3e-3 relative L2 of
+    the FP64 network with x Phi(x), for the initial weights and for weights
+    twice as large, on standard-normal standardised inputs."""
+    import kernel_gelu as K
+    rng = np.random.default_rng(0)
+    xs = rng.standard_normal((20000, 10))
+    for scale in (1.0, 2.0):
+        th = C.init_params(11) * scale
+        ref = C.forward(th, xs)
+        got = K.forward16_rounded(C.unpack, th, xs)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err < 3e-3, (scale, err)
+
+
 def test_backprop_matches_finite_differences():
     rng = np.random.default_rng(0)
     layers = (10, 8, 7, 6, 6)
