@@ -127,8 +127,13 @@ def _norms(feat, tau):
     return np.concatenate([fm, fs, tm, ts])
 
 
-@pytest.mark.parametrize("physics", [False, True])
-def test_inference_matches_oracle(E, physics):
+@pytest.mark.parametrize("physics,shape", [(False, (32, 33, 32)), (True, (32, 33, 32)),
+                                           # rows of 40 points (two full 16-point tiles and a
+                                           # partial one), x and z lines on run-time radix plans
+                                           (True, (24, 17, 40)),
+                                           # x by the dense operator (21 nodes), one partial tile
+                                           (False, (21, 9, 12))])
+def test_inference_matches_oracle(E, physics, shape):
     """The closure against the FP64 reference with the exact GELU, as the
     plain network and with the gradient-model term (coefficients Delta_k^2
     / 12 of the grid's filter). Inference runs FP16 weights and activations
@@ -138,7 +143,7 @@ def test_inference_matches_oracle(E, physics):
     the fit against the same network with x Phi(x); the fit itself is
     bounded on the CPU). The gradient-model term is FP32 arithmetic on the
     raw features."""
-    cfg = synth.config("dns192", nx=32, nz=32, ny=33)
+    cfg = synth.config("dns192", nx=shape[0], ny=shape[1], nz=shape[2])
     y, u = synth.make_snapshot(cfg, 4)
     ub64, tau64 = R.sgs_stress(u, R.Operators.from_config(cfg))
     ub = ub64.astype(np.float32)
@@ -160,7 +165,7 @@ def test_inference_matches_oracle(E, physics):
     fit_rel = _rel(kernel_gelu.forward16(C.unpack, th32, xs) * norms[26:32], ref_std * norms[26:32])
     got = pred.reshape(6, -1).T
     e_exact, e_emu = _rel(got, ref), _rel(got, emu)
-    print(f"inference (physics {physics}) rel error vs FP64 {e_exact:.2e}, vs FP16 emulation {e_emu:.2e}; "
+    print(f"inference {shape} (physics {physics}) rel error vs FP64 {e_exact:.2e}, vs FP16 emulation {e_emu:.2e}; "
           f"effect of the GELU fit {fit_rel:.2e}", flush=True)
     assert e_emu < 2e-3 and e_exact < 1e-2 + fit_rel
     assert np.allclose(_host(st), pred.mean(axis=(1, 3)), rtol=1e-10, atol=1e-14)
