@@ -448,7 +448,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     a1[t] = w16(W1 + (16 * t + col) * kMlpIn + 8 * grp, grp == 0 ? 8 : (grp == 1 ? kMlpIn - 8 : 0));
-
   }
 #pragma unroll
   for (int s = 0; s < 2; ++s) a4[s] = w16(W4 + (col < kMlpOut ? col : 0) * H + 32 * s + 8 * grp, col < kMlpOut ? 8 : 0);
