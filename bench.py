@@ -136,17 +136,30 @@ def cpu_baseline(cfg, u_host, budget_s):
                            "sample": f"{reps1} snapshot(s), {el1:.1f} s"}}, out
 
 
+def fast_transforms(cfg):
+    """The library transforms x and z by FFTs when both lengths factor into
+    2, 3 and 5 (and fit a block), else by the folded table products."""
+    def smooth(n):
+        for r in (2, 3, 5):
+            while n % r == 0:
+                n //= r
+        return n == 1
+    return all(smooth(n) and 2 <= n <= 8192 for n in (cfg.nx, cfg.nz))
+
+
 def dfilter_pass_model(cfg, nf=9, products=True):
     """Algorithmic bytes and matrix-core flops per grid point of each pass of
     the differential filter: the stress (nine filtered fields, the first pass
     forming them from u) or plain filtering / inverse filtering of nf
-    fields."""
+    fields. Fast transforms are counted by their bytes alone (their vector
+    work, O(log n) per point, is not the bound)."""
+    fast = fast_transforms(cfg)
     def fwd(n):   # folded forward transform: cosines 0..h and sines 1..hs over nodes 1..h
         h, hs = n // 2, (n - 1) // 2
-        return 2.0 * h * (h + 1 + hs) / n
+        return 0.0 if fast else 2.0 * h * (h + 1 + hs) / n
     def inv(n):   # folded inverse: P and Q sums for nodes 0..h over coefficients 1..h / 1..hs
         h, hs = n // 2, (n - 1) // 2
-        return 2.0 * (h + 1) * (h + hs) / n
+        return 0.0 if fast else 2.0 * (h + 1) * (h + hs) / n
     fb = 8.0 * nf   # one read and one write of the fields
     m = {
         # stress: reads u (3 fields), writes 9

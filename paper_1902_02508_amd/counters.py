@@ -28,6 +28,7 @@ CSRC = os.path.join(HERE, "csrc")
 # kernel symbol fragment (name, or name with template arguments) ->
 # (short name, sources it is compiled from)
 _DF = ["k_dfilt.hip", "eles_internal.h"]
+_FT = ["k_sder.hip", "eles_internal.h"]
 KERNELS = {
     "k_xz": ("k_xz", ["k_xz.hip", "eles_internal.h"]),
     "k_xzm": ("k_xzm", ["k_xzm.hip", "eles_internal.h"]),
@@ -44,8 +45,16 @@ KERNELS = {
     "k_dinv_lds<true>": ("dfilter_zi", _DF),
     "k_dinv_lds<false>": ("dfilter_xi", _DF),
     "k_depi": ("dfilter_epi", _DF),
+    # ... the same passes by fast transforms (keys ending in a comma match
+    # every instance with these leading template arguments)
+    "k_rfft<false, false,": ("dfilter_xf", _FT),
+    "k_rfft<false, true,": ("dfilter_zf", _FT),
+    "k_rfft<true, true,": ("dfilter_zi", _FT),
+    "k_rfft<true, false,": ("dfilter_xi", _FT),
 }
-_SOURCES = {name: srcs for name, srcs in KERNELS.values()}
+_SOURCES = {}
+for _name, _srcs in KERNELS.values():
+    _SOURCES.setdefault(_name, []).append(_srcs)
 
 
 def source_hash(names) -> str:
@@ -94,13 +103,18 @@ def summarize(fetch, write, copy_fetch, copy_write, mib):
     fd = _per_dispatch(fetch, "FETCH_SIZE")
     wd = _per_dispatch(write, "WRITE_SIZE")
     res = {"fetch_scale": sf, "write_scale": sw, "kernels": {}}
+    def match(d, key):
+        if key.endswith(","):
+            return [v for k, vs in d.items() if k.startswith(key) for v in vs]
+        return d.get(key, [])
     for key, (name, srcs) in KERNELS.items():
-        if key not in fd or key not in wd:
+        f, w = match(fd, key), match(wd, key)
+        if not f or not w:
             continue
-        fb = sum(fd[key]) / len(fd[key]) * 1024.0 * sf
-        wb = sum(wd[key]) / len(wd[key]) * 1024.0 * sw
+        fb = sum(f) / len(f) * 1024.0 * sf
+        wb = sum(w) / len(w) * 1024.0 * sw
         res["kernels"][name] = {"fetch_bytes": fb, "write_bytes": wb, "bytes": fb + wb,
-                                "dispatches": len(fd[key]), "source_sha256": source_hash(srcs)}
+                                "dispatches": len(f), "source_sha256": source_hash(srcs)}
     return res
 
 
@@ -120,7 +134,7 @@ def current(record, name):
     if not record or name not in record.get("kernels", {}):
         return None
     k = record["kernels"][name]
-    if name not in _SOURCES or k["source_sha256"] != source_hash(_SOURCES[name]):
+    if name not in _SOURCES or all(k["source_sha256"] != source_hash(s) for s in _SOURCES[name]):
         return None
     return k
 

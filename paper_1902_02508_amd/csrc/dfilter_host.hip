@@ -51,7 +51,7 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
   return pa < pb + nb && pb < pa + na;
 }
 
-enum { D_Y, D_D64, D_P64, D_S64, D_FX, D_IX, D_FZ, D_IZ, D_LO, D_OP, D_CP, D_INV, D_PROF, D_END };
+enum { D_Y, D_D64, D_P64, D_S64, D_FX, D_IX, D_FZ, D_IZ, D_LO, D_OP, D_CP, D_INV, D_PROF, D_TWX, D_TWZ, D_END };
 
 struct DPlan {
   eles::DAxis ax, az;
@@ -89,7 +89,9 @@ int32_t plan_d(const eles_dfilter_desc *d, DPlan *p) {
                             6 * ny * 4,
                             nfac * 4,
                             nfac * 4,
-                            3 * ny * 4};
+                            3 * ny * 4,
+                            (size_t)d->nx * 8,
+                            (size_t)d->nz * 8};
   size_t o = 0;
   for (int k = 0; k < D_END; ++k) {
     p->off[k] = o;
@@ -147,7 +149,13 @@ int32_t dfilter_setup(const eles_dfilter_desc *desc, void *state, size_t state_b
   v.cp = (float *)(s + p.off[D_CP]);
   v.inv = (float *)(s + p.off[D_INV]);
   v.prof = (float *)(s + p.off[D_PROF]);
-  if (eles::dfilter_lds_limit(v) != hipSuccess ||
+  // fast transforms where both periodic lengths factor into 2, 3 and 5
+  if (!eles::sder_plan(v.nx, v.lx, false, &v.rx) || !eles::sder_plan(v.nz, v.lz, true, &v.rz))
+    v.rx.nrad = v.rz.nrad = 0;
+  v.rx.tw = (float2 *)(s + p.off[D_TWX]);
+  v.rz.tw = (float2 *)(s + p.off[D_TWZ]);
+  if (eles::dfilter_lds_limit(v) != hipSuccess || eles::rfft_setup(v.rx, stream) != hipSuccess ||
+      eles::rfft_setup(v.rz, stream) != hipSuccess ||
       hipMemcpyAsync(v.y64, f->y.data(), f->y.size() * sizeof(double), hipMemcpyHostToDevice, stream) !=
           hipSuccess ||
       eles::launch_dsetup(v, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {

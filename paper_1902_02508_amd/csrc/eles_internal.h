@@ -164,6 +164,23 @@ struct SderArgs {
   int nx, ny, nz, zaxis;
 };
 bool sder_plan(int n, double length, bool zaxis, SderAxis *a);
+// Real forward / inverse transforms along x or z of nf fields in the folded
+// layout of the differential filter (k_sder.hip): cosine k at position k,
+// sine k at n/2 + k. prod: the x forward of the stress forms field f of the
+// nine from u [3][...] (u1 shifted by prof[y]).
+struct RfftArgs {
+  SderAxis ax;
+  const float *in;
+  float *out;
+  const float *prof;
+  long in_fs, out_fs;
+  int nx, ny, nz, nf, prod;
+  unsigned zmask;   // x inverse: fields (bit f) whose wall rows are zero
+};
+hipError_t rfft_setup(const SderAxis &a, hipStream_t s);
+hipError_t launch_rfft(const SderAxis &a, bool zaxis, bool inverse, const float *in, float *out, const float *prof,
+                       long in_fs, long out_fs, int nx, int ny, int nz, int nf, bool prod, unsigned zmask,
+                       hipStream_t s);
 size_t sder_lds_bytes(const SderAxis &a);
 
 struct GradView {
@@ -303,6 +320,7 @@ struct DView {
   float *cp, *inv;              // [2][hx + 1][ny][hz + 1] elimination factors
   float *prof;                  // [3][ny] m, M = F(m), F(m^2) - M^2
   size_t ldsmax;                // largest table slice the LDS kernels may stage (bytes)
+  SderAxis rx, rz;              // fast transforms along x and z (nrad 0: the table products)
 };
 hipError_t dfilter_lds_limit(DView &v);   // sets v.ldsmax for the current device
 hipError_t launch_dsetup(const DView &v, hipStream_t s);

@@ -1238,11 +1238,21 @@ template <bool SGS, bool APPLY = false>
 hipError_t run_filter(const DView &v, const float *in, int nf, unsigned pmask, float *w0, float *w1, float *out,
                       hipStream_t s, const hipEvent_t *ev) {
   const int nb = SGS ? kDFields : nf;
+  // fast transforms (k_sder.hip) where both lengths allow, else the folded
+  // table products on the matrix cores
+  const bool fast = v.rx.nrad && v.rz.nrad;   // odd stress fields: u2, u1'u2, u2u3 (mask 0x92)
+  const long fs = (long)v.nx * v.ny * v.nz;
   mark(ev, 2 * kDPassXf, s);
-  fwd<false, SGS>(targs(v, true, v.fx, in, w1, nb), s);
+  if (fast)
+    launch_rfft(v.rx, false, false, in, w1, v.prof, fs, fs, v.nx, v.ny, v.nz, nb, SGS, 0u, s);
+  else
+    fwd<false, SGS>(targs(v, true, v.fx, in, w1, nb), s);
   mark(ev, 2 * kDPassXf + 1, s);
   mark(ev, 2 * kDPassZf, s);
-  fwd<true, false>(targs(v, false, v.fz, w1, w0, nb), s);
+  if (fast)
+    launch_rfft(v.rz, true, false, w1, w0, nullptr, fs, fs, v.nx, v.ny, v.nz, nb, false, 0u, s);
+  else
+    fwd<true, false>(targs(v, false, v.fz, w1, w0, nb), s);
   mark(ev, 2 * kDPassZf + 1, s);
   const int ns = SGS ? 6 : nf;
   mark(ev, 2 * kDPassY, s);
@@ -1252,10 +1262,16 @@ hipError_t run_filter(const DView &v, const float *in, int nf, unsigned pmask, f
     k_dsolve<SGS><<<grid_of((long)ns * v.nx * v.nz, 256), 256, 0, s>>>(v, w0, w1, nf, pmask);
   mark(ev, 2 * kDPassY + 1, s);
   mark(ev, 2 * kDPassZi, s);
-  inv<true>(targs(v, false, v.iz, w1, w0, nb), s);
+  if (fast)
+    launch_rfft(v.rz, true, true, w1, w0, nullptr, fs, fs, v.nx, v.ny, v.nz, nb, false, 0u, s);
+  else
+    inv<true>(targs(v, false, v.iz, w1, w0, nb), s);
   mark(ev, 2 * kDPassZi + 1, s);
   mark(ev, 2 * kDPassXi, s);
-  inv<false>(targs(v, true, v.ix, w0, out, nb), s);
+  if (fast)
+    launch_rfft(v.rx, false, true, w0, out, nullptr, fs, fs, v.nx, v.ny, v.nz, nb, false, SGS ? 0x92u : pmask, s);
+  else
+    inv<false>(targs(v, true, v.ix, w0, out, nb), s);
   mark(ev, 2 * kDPassXi + 1, s);
   return hipGetLastError();
 }

@@ -241,12 +241,20 @@ __device__ inline void gstore(const Tile &t, int x, int p, cpx v) {
   }
 }
 
+// Global access of a block's lines: two real lines as one complex line.
+template <bool Z>
+struct PairIO {
+  __device__ cpx load(const Tile &t, int x, int p) const { return gload<Z>(t, x, p); }
+  __device__ void store(const Tile &t, int x, int p, cpx v) const { gstore<Z>(t, x, p, v); }
+};
+
 // One pass of radix R. SRC: 0 global, 1 LDS, 2 registers (the carried
 // items); DST: 0 global, 1 LDS, 2 registers. Items are tid + it * T;
 // rsync: wait for every thread's LDS reads before the writes (in place).
-template <bool Z, int E, int T, int R, int S, int SRC, int DST>
+// io: the global loads (SRC 0) and stores (DST 0).
+template <bool Z, int E, int T, int R, int S, int SRC, int DST, class IO = PairIO<Z>>
 __device__ __attribute__((always_inline)) inline void pass(const Tile &t, cpx (&v)[E], cpx *lds, const cpx *tw, int Ns, uint32_t mnr,
-                            uint32_t mns, bool rsync) {
+                            uint32_t mns, bool rsync, const IO &io = IO()) {
   constexpr int IT = E / R;
   const int n = t.n, nR = n / R, items = t.P * nR;
   const int tid = threadIdx.x;
@@ -261,7 +269,7 @@ __device__ __attribute__((always_inline)) inline void pass(const Tile &t, cpx (&
         for (int r = 0; r < R; ++r) {
           const int x = j + r * nR;
           if (SRC == 0) {
-            v[it * R + r] = gload<Z>(t, x, p);
+            v[it * R + r] = io.load(t, x, p);
           } else {
             const float2 q = reinterpret_cast<const float2 *>(lds)[lds_at<Z>(t, x, p)];
             v[it * R + r] = cpx{q.x, q.y};
@@ -296,7 +304,7 @@ __device__ __attribute__((always_inline)) inline void pass(const Tile &t, cpx (&
         for (int q = 0; q < R; ++q) {
           const int x = base + q * Ns;
           if (DST == 0) {
-            gstore<Z>(t, x, p, a[q]);
+            io.store(t, x, p, a[q]);
           } else {
             reinterpret_cast<float2 *>(lds)[lds_at<Z>(t, x, p)] = make_float2(a[q].re, a[q].im);
           }
@@ -456,6 +464,200 @@ __global__ void __launch_bounds__(T) k_sder(SderArgs g) {
   }
 }
 
+// ---- real transforms (the differential filter's x and z transforms)
+//
+// Two real lines a, b travel as z = a + i b. Forward: Z = DFT(z) with
+// exp(-2 pi i k x / n), then A_k = (Z_k + conj Z_{n-k}) / 2 and B_k = (Z_k -
+// conj Z_{n-k}) / (2 i) are the transforms of a and b, and the folded real
+// coefficients of a line are C_k = Re A_k at position k (k = 0 .. n/2) and
+// S_k = -Im A_k at position n/2 + k (k = 1 .. (n - 1)/2): the sums of the
+// line times cos and sin (2 pi k x / n). Inverse: A_k = C_k - i S_k for k <=
+// n/2, A_{n-k} = conj A_k, the same for B, z = DFT^-1(A + i B) / n.
+
+// forward input: the field's two real lines, or (the x transform of the
+// stress) the field formed from u: u_a' or u_a' u_b', with u1' = u1 - m(y)
+template <bool Z>
+struct FwdIO {
+  const float *ua, *ub;   // products: the factors' lines at the tile's origin; else null
+  float sa, sb;           // shifts subtracted from the factors
+  bool two;               // a product of two factors
+  __device__ cpx load(const Tile &t, int x, int p) const {
+    if (!ua) return gload<Z>(t, x, p);
+    cpx v{0.0f, 0.0f};
+    const int h = 2 * p;
+    const long o = (long)x * t.xs + h;
+    if (h < t.lim) {
+      const float a = ua[o] - sa;
+      v.re = two ? a * (ub[o] - sb) : a;
+    }
+    if (h + 1 < t.lim) {
+      const float a = ua[o + 1] - sa;
+      v.im = two ? a * (ub[o + 1] - sb) : a;
+    }
+    return v;
+  }
+  __device__ void store(const Tile &, int, int, cpx) const {}
+};
+
+// inverse input: Z_k = A_k + i B_k from the folded coefficients of both
+// lines; output: the two real lines scaled by 1/n
+template <bool Z>
+struct InvIO {
+  int h, hs;
+  float scale;
+  bool zero;   // the lines are wall rows of an odd field: exactly zero
+  __device__ cpx load(const Tile &t, int k, int p) const {
+    const bool up = k > h;
+    const int kk = up ? t.n - k : k;
+    const cpx c = gload<Z>(t, kk, p);
+    const cpx sn = kk >= 1 && kk <= hs ? gload<Z>(t, h + kk, p) : cpx{0.0f, 0.0f};
+    const cpx A{c.re, up ? sn.re : -sn.re}, B{c.im, up ? sn.im : -sn.im};
+    return cpx{A.re - B.im, A.im + B.re};
+  }
+  __device__ void store(const Tile &t, int x, int p, cpx v) const {
+    gstore<Z>(t, x, p, zero ? cpx{0.0f, 0.0f} : cpx{v.re * scale, v.im * scale});
+  }
+};
+
+// A_k, B_k from the natural-order Z in LDS, as folded coefficients
+template <bool Z, int T>
+__device__ inline void fwd_epilogue(const Tile &t, const cpx *lds, int h, int hs) {
+  const int n = t.n, items = t.P * (h + 1);
+  for (int w = threadIdx.x; w < items; w += T) {
+    int p, k;
+    if (!Z) {
+      p = w & (t.P - 1);
+      k = w >> t.lp;
+    } else {
+      p = w / (h + 1);
+      k = w - p * (h + 1);
+    }
+    const float2 zk = reinterpret_cast<const float2 *>(lds)[lds_at<Z>(t, k, p)];
+    const float2 zm = reinterpret_cast<const float2 *>(lds)[lds_at<Z>(t, k == 0 ? 0 : n - k, p)];
+    const cpx A{0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
+    const cpx B{0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x)};
+    gstore<Z>(t, k, p, cpx{A.re, B.re});
+    if (k >= 1 && k <= hs) gstore<Z>(t, h + k, p, cpx{-A.im, -B.im});
+  }
+}
+
+// pass s of a forward (S = -1: global in, LDS out, natural order after the
+// last pass) or inverse (S = +1: global in and out) transform
+template <bool Z, int E, int T, int S, int R, class IO>
+__device__ __attribute__((always_inline)) inline void tstep_r(const Tile &t, cpx (&v)[E], cpx *lds, const cpx *tw,
+                                                              int s, int nr, int Ns, uint32_t mnr, uint32_t mns,
+                                                              const IO &io) {
+  const bool first = s == 0, last = s == nr - 1;
+  if (S < 0) {
+    if (first) pass<Z, E, T, R, S, 0, 1, IO>(t, v, lds, tw, Ns, mnr, mns, false, io);
+    else pass<Z, E, T, R, S, 1, 1, IO>(t, v, lds, tw, Ns, mnr, mns, true, io);
+  } else {
+    if (first && last) pass<Z, E, T, R, S, 0, 0, IO>(t, v, lds, tw, Ns, mnr, mns, false, io);
+    else if (first) pass<Z, E, T, R, S, 0, 1, IO>(t, v, lds, tw, Ns, mnr, mns, false, io);
+    else if (last) pass<Z, E, T, R, S, 1, 0, IO>(t, v, lds, tw, Ns, mnr, mns, false, io);
+    else pass<Z, E, T, R, S, 1, 1, IO>(t, v, lds, tw, Ns, mnr, mns, true, io);
+  }
+}
+
+template <bool Z, int E, int T, int S, class IO>
+__device__ __attribute__((always_inline)) inline void tstep(int R, const Tile &t, cpx (&v)[E], cpx *lds,
+                                                            const cpx *tw, int s, int nr, int Ns, uint32_t mnr,
+                                                            uint32_t mns, const IO &io) {
+  switch (R) {
+    case 16: tstep_r<Z, E, T, S, 16>(t, v, lds, tw, s, nr, Ns, mnr, mns, io); break;
+    case 8: tstep_r<Z, E, T, S, 8>(t, v, lds, tw, s, nr, Ns, mnr, mns, io); break;
+    case 4: tstep_r<Z, E, T, S, 4>(t, v, lds, tw, s, nr, Ns, mnr, mns, io); break;
+    case 2: tstep_r<Z, E, T, S, 2>(t, v, lds, tw, s, nr, Ns, mnr, mns, io); break;
+    case 3: tstep_r<Z, E, T, S, 3>(t, v, lds, tw, s, nr, Ns, mnr, mns, io); break;
+    default: tstep_r<Z, E, T, S, 5>(t, v, lds, tw, s, nr, Ns, mnr, mns, io); break;
+  }
+}
+
+template <bool Z, int E, int T, int S, class PL, class IO>
+__device__ __attribute__((always_inline)) inline void transform(const SderAxis &A, const Tile &t, cpx (&v)[E],
+                                                                cpx *lds, const cpx *tw, const IO &io) {
+  if constexpr (PL::np > 0) {
+    constexpr int nr = PL::np;
+    int Ns = 1;
+#pragma unroll
+    for (int s = 0; s < nr; ++s) {
+      tstep<Z, E, T, S>(PL::at(s), t, v, lds, tw, s, nr, Ns, A.mnr[s], A.mns[s], io);
+      Ns *= PL::at(s);
+    }
+  } else {
+    const int nr = A.nrad;
+    int Ns = 1;
+    for (int s = 0; s < nr; ++s) {
+      tstep<Z, E, T, S>(A.rad[s], t, v, lds, tw, s, nr, Ns, A.mnr[s], A.mns[s], io);
+      Ns *= A.rad[s];
+    }
+  }
+}
+
+// nf fields [nf][nx][ny][nz]: x lines (tile = ((y nzt + zt) nf + f), the
+// fields of one tile on neighbouring blocks, which share u when the fields
+// are formed from it) or z lines (tile = rt nf + f)
+template <bool INV, bool Z, int E, int T, class PL>
+__global__ void __launch_bounds__(T) k_rfft(RfftArgs g) {
+  extern __shared__ float2 rfft_lds[];
+  const SderAxis &A = g.ax;
+  int n;
+  if constexpr (PL::np > 0) n = PL::len();
+  else n = A.n;
+  cpx *lds = reinterpret_cast<cpx *>(rfft_lds);
+  cpx *tw = lds + ((A.P * n + 31) & ~31);
+  for (int m = threadIdx.x; m < n; m += T) {
+    const float2 q = A.tw[m];
+    tw[m] = cpx{q.x, q.y};
+  }
+  const long tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  Tile t;
+  t.P = A.P;
+  t.lp = A.lp;
+  t.n = n;
+  t.vec = false;
+  const long plane = (long)g.ny * g.nz;
+  const int f = (int)(tile % g.nf);
+  const long rest = tile / g.nf;
+  FwdIO<Z> fio{nullptr, nullptr, 0.0f, 0.0f, false};
+  bool zero = false;
+  long o;
+  if (!Z) {
+    const int nzt = (g.nz + 2 * A.P - 1) / (2 * A.P);
+    const int zt = (int)(rest % nzt), y = (int)(rest / nzt);
+    // the paired lines' rounding would leave traces of the neighbouring
+    // lines on the wall rows of odd fields, which are zero by parity
+    zero = INV && ((g.zmask >> f) & 1u) && (y == 0 || y == g.ny - 1);
+    o = (long)y * g.nz + 2L * A.P * zt;
+    t.xs = plane;
+    t.lim = g.nz - 2 * A.P * zt;
+    t.vec = (g.nz & 1) == 0 && (g.in_fs & 1) == 0 && (g.out_fs & 1) == 0;
+    if (!INV && g.prod) {
+      // stress field f: u1', u2, u3, u1'u1', u1'u2, u1'u3, u2u2, u2u3, u3u3
+      const int ca = f < 3 ? f : (f < 6 ? 0 : (f < 8 ? 1 : 2));
+      const int cb = f < 3 ? f : (f < 6 ? f - 3 : (f == 6 ? 1 : 2));
+      const float m = g.prof[y];
+      fio = FwdIO<Z>{g.in + ca * g.in_fs + o, g.in + cb * g.in_fs + o, ca == 0 ? m : 0.0f, cb == 0 ? m : 0.0f,
+                     f >= 3};
+    }
+  } else {
+    const long rows = (long)g.nx * g.ny;
+    o = rest * 2 * A.P * g.nz;
+    t.xs = g.nz;
+    t.lim = (int)min((long)2 * A.P, rows - rest * 2 * A.P);
+  }
+  t.in = g.in + f * g.in_fs + o;
+  t.out = g.out + f * g.out_fs + o;
+  const int h = n / 2, hs = (n - 1) / 2;
+  cpx v[E];
+  if (!INV) {
+    transform<Z, E, T, -1, PL>(A, t, v, lds, tw, fio);
+    fwd_epilogue<Z, T>(t, lds, h, hs);
+  } else {
+    transform<Z, E, T, 1, PL>(A, t, v, lds, tw, InvIO<Z>{h, hs, 1.0f / (float)n, zero});
+  }
+}
+
 // exp(-2 pi i m / n) in FP64, rounded to FP32
 __global__ void __launch_bounds__(256) k_sder_tw(int n, float2 *tw) {
   const int m = blockIdx.x * 256 + threadIdx.x;
@@ -499,6 +701,34 @@ SderKernel sder_pick(const SderAxis &a, bool zaxis) {
 }
 
 }  // namespace
+
+typedef void (*RfftKernel)(RfftArgs);
+
+template <bool Z, int E, int T, bool INV>
+RfftKernel rfft_kernel(const SderAxis &a) {
+  switch (sder_fixed(a.rad, a.nrad)) {
+    case 1: return k_rfft<INV, Z, E, T, Rad<16, 16, 4>>;
+    case 2: return k_rfft<INV, Z, E, T, Rad<16, 16, 3>>;
+    case 3: return k_rfft<INV, Z, E, T, Rad<16, 16, 2>>;
+    case 4: return k_rfft<INV, Z, E, T, Rad<16, 4, 3>>;
+    default: return nullptr;
+  }
+}
+
+template <bool INV>
+RfftKernel rfft_pick_t(const SderAxis &a, bool zaxis) {
+  if (!sder_fixed(a.rad, a.nrad)) {
+    if (zaxis) return a.E == 16 ? k_rfft<INV, true, 16, 256, Rad<>> : k_rfft<INV, true, 32, 256, Rad<>>;
+    return a.E == 16 ? k_rfft<INV, false, 16, 256, Rad<>> : k_rfft<INV, false, 32, 256, Rad<>>;
+  }
+  if (zaxis) return a.E == 16 ? rfft_kernel<true, 16, 256, INV>(a) : rfft_kernel<true, 32, 256, INV>(a);
+  if (a.T == 512) return a.E == 16 ? rfft_kernel<false, 16, 512, INV>(a) : rfft_kernel<false, 32, 512, INV>(a);
+  return a.E == 16 ? rfft_kernel<false, 16, 256, INV>(a) : rfft_kernel<false, 32, 256, INV>(a);
+}
+
+RfftKernel rfft_pick(const SderAxis &a, bool zaxis, bool inverse) {
+  return inverse ? rfft_pick_t<true>(a, zaxis) : rfft_pick_t<false>(a, zaxis);
+}
 
 size_t sder_lds_bytes(const SderAxis &a) { return (size_t)(((a.P * a.n + 31) & ~31) + a.n) * 8; }
 
@@ -588,6 +818,41 @@ hipError_t launch_sder(const GradView &v, bool zaxis, const float *ubar, float *
   const long tiles = zaxis ? 3L * (((long)v.nx * v.ny + P2 - 1) / P2) : 3L * v.ny * ((v.nz + P2 - 1) / P2);
   if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
   sder_pick(g.ax, zaxis)<<<(unsigned)tiles, g.ax.T, sder_lds_bytes(g.ax), s>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t rfft_setup(const SderAxis &a, hipStream_t s) {
+  if (!a.nrad) return hipSuccess;
+  k_sder_tw<<<(unsigned)((a.n + 255) / 256), 256, 0, s>>>(a.n, a.tw);
+  hipError_t e = hipGetLastError();
+  const size_t bytes = sder_lds_bytes(a);
+  for (int k = 0; k < 4 && e == hipSuccess && bytes > 65536; ++k)
+    e = hipFuncSetAttribute((const void *)rfft_pick(a, k & 1, k >> 1), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes);
+  return e;
+}
+
+hipError_t launch_rfft(const SderAxis &a, bool zaxis, bool inverse, const float *in, float *out, const float *prof,
+                       long in_fs, long out_fs, int nx, int ny, int nz, int nf, bool prod, unsigned zmask,
+                       hipStream_t s) {
+  if (!a.nrad || nf < 1 || (prod && (zaxis || inverse || nf != 9))) return hipErrorInvalidValue;
+  RfftArgs g;
+  g.zmask = zmask;
+  g.ax = a;
+  g.in = in;
+  g.out = out;
+  g.prof = prof;
+  g.in_fs = in_fs;
+  g.out_fs = out_fs;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.nf = nf;
+  g.prod = prod ? 1 : 0;
+  const int P2 = 2 * a.P;
+  const long tiles = zaxis ? (long)nf * (((long)nx * ny + P2 - 1) / P2) : (long)nf * ny * ((nz + P2 - 1) / P2);
+  if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
+  rfft_pick(a, zaxis, inverse)<<<(unsigned)tiles, a.T, sder_lds_bytes(a), s>>>(g);
   return hipGetLastError();
 }
 
