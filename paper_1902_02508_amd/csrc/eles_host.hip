@@ -880,6 +880,15 @@ int32_t gradient_features(eles_filter f, const float *ubar, float *feat, bool wa
   } else if (dense_dx(f, ubar, feat, stream) != ELES_OK) {
     return ELES_EHIP;
   }
+  // d/dz with d/dy from the same staged rows where the fused kernel covers
+  // the grid
+  if (eles::sder_zy_ok(g)) {
+    if (eles::launch_sder_zy(g, ubar, feat + 2 * n, feat + n, (long)(3 * n), 0x2, stream) != hipSuccess)
+      return ELES_EHIP;
+    if (walldist && eles::launch_walldist(f->v.y64, nx, ny, nz, feat + 9 * n, stream) != hipSuccess)
+      return ELES_EHIP;
+    return ELES_OK;
+  }
   // d/dy: three-point difference with the parities of (u1, u2, u3),
   // streamed along each column (grids of three or more rows)
   if (ny >= 3) {

@@ -162,6 +162,13 @@ struct SderArgs {
   float *out;
   long in_fs, out_fs;
   int nx, ny, nz, zaxis;
+  // z lines only: also d/dy of the three fields into dy + f * out_fs, the
+  // three-point rows of D[parity] (row pitch kp; parity bit f of pmask), or
+  // dy null
+  float *dy;
+  const float *D[2];
+  int kp;
+  unsigned pmask;
 };
 bool sder_plan(int n, double length, bool zaxis, SderAxis *a);
 // Real forward / inverse transforms along x or z of nf fields in the folded
@@ -207,6 +214,11 @@ hipError_t sder_setup(const SderAxis &a, hipStream_t s);
 // out + f * out_fstride by fast transforms; needs the axis's nrad > 0
 hipError_t launch_sder(const GradView &v, bool zaxis, const float *ubar, float *out, long out_fstride,
                        hipStream_t s);
+// d/dz as launch_sder, with d/dy of the three fields (odd fields in pmask)
+// into dy + f * out_fstride from the same staged rows; needs ny >= 3
+hipError_t launch_sder_zy(const GradView &v, const float *ubar, float *out, float *dy, long out_fstride,
+                          unsigned pmask, hipStream_t s);
+bool sder_zy_ok(const GradView &v);   // the fused kernel covers this grid
 hipError_t launch_walldist(const double *y64, int nx, int ny, int nz, float *out, hipStream_t s);
 
 // ---- the perceptron

@@ -244,7 +244,20 @@ __device__ inline void gstore(const Tile &t, int x, int p, cpx v) {
 // Global access of a block's lines: two real lines as one complex line.
 template <bool Z>
 struct PairIO {
+  static constexpr bool kLds = false;   // loads from LDS the pass then overwrites
   __device__ cpx load(const Tile &t, int x, int p) const { return gload<Z>(t, x, p); }
+  __device__ void store(const Tile &t, int x, int p, cpx v) const { gstore<Z>(t, x, p, v); }
+};
+
+// z lines read from rows staged in LDS, row 2p + h at raw[(2 p + h + 1) n]
+// (row -1 and row 2P are the neighbours of the tile)
+template <bool Z>
+struct RawIO {
+  static constexpr bool kLds = true;
+  const float *raw;
+  __device__ cpx load(const Tile &t, int x, int p) const {
+    return cpx{raw[(2 * p + 1) * t.n + x], raw[(2 * p + 2) * t.n + x]};
+  }
   __device__ void store(const Tile &t, int x, int p, cpx v) const { gstore<Z>(t, x, p, v); }
 };
 
@@ -277,7 +290,7 @@ __device__ __attribute__((always_inline)) inline void pass(const Tile &t, cpx (&
         }
       }
     }
-    if (SRC == 1 && rsync) __syncthreads();
+    if ((SRC == 1 || IO::kLds) && rsync) __syncthreads();
   }
   const int stride = Ns > 1 ? n / (Ns * R) : 0;
 #pragma unroll
@@ -341,13 +354,14 @@ __device__ __attribute__((always_inline)) inline void deriv(const Tile &t, cpx (
 
 // Pass s of the forward (S = -1) or inverse (S = +1) transform with radix R
 // of nr passes; after the last forward pass the derivative factors.
-template <bool Z, int E, int T, int S, int R>
+template <bool Z, int E, int T, int S, int R, class IO = PairIO<Z>>
 __device__ __attribute__((always_inline)) inline void step_r(const Tile &t, cpx (&v)[E], cpx *lds, const cpx *tw, int s, int nr, int Ns,
-                              uint32_t mnr, uint32_t mns, float cfac) {
+                              uint32_t mnr, uint32_t mns, float cfac, const IO &io = IO()) {
   const bool first = s == 0, last = s == nr - 1;
   if (S < 0) {
-    if (first && last) pass<Z, E, T, R, S, 0, 2>(t, v, lds, tw, Ns, mnr, mns, false);
-    else if (first) pass<Z, E, T, R, S, 0, 1>(t, v, lds, tw, Ns, mnr, mns, false);
+    // a first pass reading LDS rows it then overwrites waits for every read
+    if (first && last) pass<Z, E, T, R, S, 0, 2, IO>(t, v, lds, tw, Ns, mnr, mns, false, io);
+    else if (first) pass<Z, E, T, R, S, 0, 1, IO>(t, v, lds, tw, Ns, mnr, mns, IO::kLds, io);
     else if (last) pass<Z, E, T, R, S, 1, 2>(t, v, lds, tw, Ns, mnr, mns, true);
     else pass<Z, E, T, R, S, 1, 1>(t, v, lds, tw, Ns, mnr, mns, true);
     if (last) deriv<Z, E, T, R>(t, v, cfac, mnr);
@@ -359,16 +373,16 @@ __device__ __attribute__((always_inline)) inline void step_r(const Tile &t, cpx 
   }
 }
 
-template <bool Z, int E, int T, int S>
+template <bool Z, int E, int T, int S, class IO = PairIO<Z>>
 __device__ __attribute__((always_inline)) inline void step(int R, const Tile &t, cpx (&v)[E], cpx *lds, const cpx *tw, int s, int nr, int Ns,
-                            uint32_t mnr, uint32_t mns, float cfac) {
+                            uint32_t mnr, uint32_t mns, float cfac, const IO &io = IO()) {
   switch (R) {
-    case 16: step_r<Z, E, T, S, 16>(t, v, lds, tw, s, nr, Ns, mnr, mns, cfac); break;
-    case 8: step_r<Z, E, T, S, 8>(t, v, lds, tw, s, nr, Ns, mnr, mns, cfac); break;
-    case 4: step_r<Z, E, T, S, 4>(t, v, lds, tw, s, nr, Ns, mnr, mns, cfac); break;
-    case 2: step_r<Z, E, T, S, 2>(t, v, lds, tw, s, nr, Ns, mnr, mns, cfac); break;
-    case 3: step_r<Z, E, T, S, 3>(t, v, lds, tw, s, nr, Ns, mnr, mns, cfac); break;
-    default: step_r<Z, E, T, S, 5>(t, v, lds, tw, s, nr, Ns, mnr, mns, cfac); break;
+    case 16: step_r<Z, E, T, S, 16, IO>(t, v, lds, tw, s, nr, Ns, mnr, mns, cfac, io); break;
+    case 8: step_r<Z, E, T, S, 8, IO>(t, v, lds, tw, s, nr, Ns, mnr, mns, cfac, io); break;
+    case 4: step_r<Z, E, T, S, 4, IO>(t, v, lds, tw, s, nr, Ns, mnr, mns, cfac, io); break;
+    case 2: step_r<Z, E, T, S, 2, IO>(t, v, lds, tw, s, nr, Ns, mnr, mns, cfac, io); break;
+    case 3: step_r<Z, E, T, S, 3, IO>(t, v, lds, tw, s, nr, Ns, mnr, mns, cfac, io); break;
+    default: step_r<Z, E, T, S, 5, IO>(t, v, lds, tw, s, nr, Ns, mnr, mns, cfac, io); break;
   }
 }
 
@@ -389,7 +403,7 @@ struct Rad<> {
   static constexpr int np = 0;
 };
 
-template <bool Z, int E, int T, class PL>
+template <bool Z, int E, int T, class PL, bool DY = false>
 __global__ void __launch_bounds__(T) k_sder(SderArgs g) {
   extern __shared__ float2 sder_lds[];
   const SderAxis &A = g.ax;
@@ -397,7 +411,9 @@ __global__ void __launch_bounds__(T) k_sder(SderArgs g) {
   if constexpr (PL::np > 0) n = PL::len();
   else n = A.n;
   cpx *lds = reinterpret_cast<cpx *>(sder_lds);
-  cpx *tw = lds + ((A.P * n + 31) & ~31);
+  // with d/dy the data region first holds the tile's rows and their two
+  // neighbours, 2P + 2 rows of n floats
+  cpx *tw = lds + (((A.P + (DY ? 1 : 0)) * n + 31) & ~31);
   for (int m = threadIdx.x; m < n; m += T) {
     const float2 q = A.tw[m];
     tw[m] = cpx{q.x, q.y};
@@ -431,8 +447,108 @@ __global__ void __launch_bounds__(T) k_sder(SderArgs g) {
     t.out = g.out + f * g.out_fs + o;
     t.xs = g.nz;
     t.lim = (int)min((long)2 * A.P, rows - rt * 2 * A.P);
+    if constexpr (DY) {
+      // d/dy: rows r0 - 1 .. r0 + 2P of the field into LDS (zeros past the
+      // field), eight loads in flight per thread, and the weights of each
+      // tile row for its y (the wall rows use the mirror rows folded into D)
+      // beside them; then each tile row from its neighbours
+      float *raw = reinterpret_cast<float *>(lds);
+      float *wts = reinterpret_cast<float *>(tw + n);
+      const long r0 = rt * 2 * A.P;
+      const float *src = g.in + f * g.in_fs;
+      const long e_at = (r0 - 1) * g.nz;   // raw element e is field element e_at + e
+      const long lo = r0 == 0 ? n : 0, hi = (rows - r0 + 1) * (long)n;
+      const int total = (2 * A.P + 2) * n;
+      for (int e0 = 0; e0 < total; e0 += 8 * T) {
+        float r[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int e = e0 + k * T + (int)threadIdx.x;
+          r[k] = e < total && e >= lo && e < hi ? src[e_at + e] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int e = e0 + k * T + (int)threadIdx.x;
+          if (e < total) raw[e] = r[k];
+        }
+      }
+      const float *D = g.D[(g.pmask >> f) & 1u];
+      if ((int)threadIdx.x < t.lim) {
+        const int q = threadIdx.x;
+        const int y = (int)((r0 + q) % g.ny);
+        float d0 = 0.0f, d1, d2 = 0.0f, kind = 0.0f;   // kind: 0 interior, 1 y = 0, 2 y = ny - 1
+        if (y == 0) {
+          d1 = D[0];
+          d2 = D[1];
+          kind = 1.0f;
+        } else if (y == g.ny - 1) {
+          const float *Dl = D + (long)y * g.kp + (y - 1);
+          d0 = Dl[0];
+          d1 = Dl[1];
+          kind = 2.0f;
+        } else {
+          const float *Dr = D + (long)y * g.kp + (y - 1);
+          d0 = Dr[0];
+          d1 = Dr[1];
+          d2 = Dr[2];
+        }
+        wts[4 * q] = d0;
+        wts[4 * q + 1] = d1;
+        wts[4 * q + 2] = d2;
+        wts[4 * q + 3] = kind;
+      }
+      __syncthreads();
+      float *dst = g.dy + f * g.out_fs + r0 * g.nz;
+      for (int q = 0; q < t.lim; ++q) {
+        const float d0 = wts[4 * q], d1 = wts[4 * q + 1], d2 = wts[4 * q + 2], kind = wts[4 * q + 3];
+        const float *um = raw + q * n, *u0 = raw + (q + 1) * n, *up = raw + (q + 2) * n;
+        float *o = dst + (long)q * g.nz;
+        // a wall row reads no row of the neighbouring column
+        if (kind == 1.0f) {
+          for (int x = threadIdx.x; x < n; x += T) o[x] = d1 * u0[x] + d2 * up[x];
+        } else if (kind == 2.0f) {
+          for (int x = threadIdx.x; x < n; x += T) o[x] = d0 * um[x] + d1 * u0[x];
+        } else {
+          for (int x = threadIdx.x; x < n; x += T) o[x] = d0 * um[x] + d1 * u0[x] + d2 * up[x];
+        }
+      }
+    }
   }
   cpx v[E];
+  [[maybe_unused]] const RawIO<Z> rio{reinterpret_cast<const float *>(lds)};
+  if constexpr (DY) {
+    static_assert(Z, "d/dy rides on the z lines");
+    if constexpr (PL::np > 0) {
+      constexpr int nr = PL::np;
+      int Ns = 1;
+#pragma unroll
+      for (int s = 0; s < nr; ++s) {
+        step<Z, E, T, -1, RawIO<Z>>(PL::at(s), t, v, lds, tw, s, nr, Ns, A.mnr[s], A.mns[s], A.cfac, rio);
+        Ns *= PL::at(s);
+      }
+      Ns = 1;
+#pragma unroll
+      for (int s = 0; s < nr; ++s) {
+        const int si = nr - 1 - s;
+        step<Z, E, T, 1, RawIO<Z>>(PL::at(si), t, v, lds, tw, s, nr, Ns, A.mnr[si], A.imns[s], A.cfac, rio);
+        Ns *= PL::at(si);
+      }
+    } else {
+      const int nr = A.nrad;
+      int Ns = 1;
+      for (int s = 0; s < nr; ++s) {
+        step<Z, E, T, -1, RawIO<Z>>(A.rad[s], t, v, lds, tw, s, nr, Ns, A.mnr[s], A.mns[s], A.cfac, rio);
+        Ns *= A.rad[s];
+      }
+      Ns = 1;
+      for (int s = 0; s < nr; ++s) {
+        const int si = nr - 1 - s;
+        step<Z, E, T, 1, RawIO<Z>>(A.rad[si], t, v, lds, tw, s, nr, Ns, A.mnr[si], A.imns[s], A.cfac, rio);
+        Ns *= A.rad[si];
+      }
+    }
+    return;
+  }
   if constexpr (PL::np > 0) {
     constexpr int nr = PL::np;
     int Ns = 1;
@@ -478,6 +594,7 @@ __global__ void __launch_bounds__(T) k_sder(SderArgs g) {
 // stress) the field formed from u: u_a' or u_a' u_b', with u1' = u1 - m(y)
 template <bool Z>
 struct FwdIO {
+  static constexpr bool kLds = false;
   const float *ua, *ub;   // products: the factors' lines at the tile's origin; else null
   float sa, sb;           // shifts subtracted from the factors
   bool two;               // a product of two factors
@@ -503,6 +620,7 @@ struct FwdIO {
 // lines; output: the two real lines scaled by 1/n
 template <bool Z>
 struct InvIO {
+  static constexpr bool kLds = false;
   int h, hs;
   float scale;
   bool zero;   // the lines are wall rows of an odd field: exactly zero
@@ -689,6 +807,18 @@ SderKernel sder_kernel(const SderAxis &a) {
   }
 }
 
+// z lines with the fused d/dy
+template <int E>
+SderKernel sder_kernel_dy(const SderAxis &a) {
+  switch (sder_fixed(a.rad, a.nrad)) {
+    case 1: return k_sder<true, E, 256, Rad<16, 16, 4>, true>;
+    case 2: return k_sder<true, E, 256, Rad<16, 16, 3>, true>;
+    case 3: return k_sder<true, E, 256, Rad<16, 16, 2>, true>;
+    case 4: return k_sder<true, E, 256, Rad<16, 4, 3>, true>;
+    default: return k_sder<true, E, 256, Rad<>, true>;
+  }
+}
+
 SderKernel sder_pick(const SderAxis &a, bool zaxis) {
   if (!sder_fixed(a.rad, a.nrad)) {
     if (zaxis) return a.E == 16 ? k_sder<true, 16, 256, Rad<>> : k_sder<true, 32, 256, Rad<>>;
@@ -814,11 +944,52 @@ hipError_t launch_sder(const GradView &v, bool zaxis, const float *ubar, float *
   g.ny = v.ny;
   g.nz = v.nz;
   g.zaxis = zaxis;
+  g.dy = nullptr;
+  g.D[0] = g.D[1] = nullptr;
+  g.kp = 0;
+  g.pmask = 0;
   const int P2 = 2 * g.ax.P;
   const long tiles = zaxis ? 3L * (((long)v.nx * v.ny + P2 - 1) / P2) : 3L * v.ny * ((v.nz + P2 - 1) / P2);
   if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
   sder_pick(g.ax, zaxis)<<<(unsigned)tiles, g.ax.T, sder_lds_bytes(g.ax), s>>>(g);
   return hipGetLastError();
+}
+
+// LDS of the z kernel with the fused d/dy: 2P + 2 staged rows in the data
+// region (no more than 64 KB: the fused kernel is not given a larger limit)
+static size_t sder_dy_lds_bytes(const SderAxis &a) {
+  return (size_t)((((a.P + 1) * a.n + 31) & ~31) + a.n) * 8 + (size_t)8 * a.P * 4;
+}
+
+hipError_t launch_sder_zy(const GradView &v, const float *ubar, float *out, float *dy, long out_fstride,
+                          unsigned pmask, hipStream_t s) {
+  const SderAxis &a = v.sz;
+  if (!a.nrad || a.T != 256 || v.ny < 3 || sder_dy_lds_bytes(a) > 65536) return hipErrorInvalidValue;
+  SderArgs g;
+  g.ax = a;
+  g.in = ubar;
+  g.out = out;
+  g.in_fs = (long)v.nx * v.ny * v.nz;
+  g.out_fs = out_fstride;
+  g.nx = v.nx;
+  g.ny = v.ny;
+  g.nz = v.nz;
+  g.zaxis = 1;
+  g.dy = dy;
+  g.D[0] = v.dy32[0];
+  g.D[1] = v.dy32[1];
+  g.kp = v.kpy;
+  g.pmask = pmask;
+  const int P2 = 2 * a.P;
+  const long tiles = 3L * (((long)v.nx * v.ny + P2 - 1) / P2);
+  if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
+  const SderKernel k = a.E == 16 ? sder_kernel_dy<16>(a) : sder_kernel_dy<32>(a);
+  k<<<(unsigned)tiles, 256, sder_dy_lds_bytes(a), s>>>(g);
+  return hipGetLastError();
+}
+
+bool sder_zy_ok(const GradView &v) {
+  return v.sz.nrad && v.sz.T == 256 && v.ny >= 3 && sder_dy_lds_bytes(v.sz) <= 65536;
 }
 
 hipError_t rfft_setup(const SderAxis &a, hipStream_t s) {

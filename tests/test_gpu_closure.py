@@ -61,7 +61,10 @@ _PI = math.pi
     ("tiny", dict(nx=30, nz=2, ny=7), True),
     ("tiny", dict(nx=1, nz=32, ny=5), True),
     # the production line lengths (1024 along x, 768 along z), and lines of
-    # 4096 and 8192 nodes (two and one complex line per block)
+    # 4096 and 8192 nodes (two and one complex line per block). Grids of
+    # three or more rows with fast z transforms take d/dy in the z kernel;
+    # z lines of 8192 nodes, which leave it no room for the staged rows,
+    # and the other grids take it in its own kernel
     ("dns192", dict(nx=1024, ny=5, nz=768, delta_x=4 * _PI / 256, delta_z=2 * _PI / 192), False),
     ("dns192", dict(nx=4096, ny=3, nz=10, delta_x=4 * _PI / 1024, delta_z=2 * _PI / 4), False),
     ("dns192", dict(nx=6, ny=3, nz=8192, delta_x=4 * _PI / 4, delta_z=2 * _PI / 2048), False)])
