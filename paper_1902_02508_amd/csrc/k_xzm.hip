@@ -28,9 +28,14 @@
 // from registers, with no exchange. The z stencil half-width is at most 16,
 // so a z tile reads its own chunk and one on each side.
 //
-// Chunks go in pairs: the two chunks of a pair are the two 64-byte halves
-// of the same 128-byte lines, requested together, so each line is fetched
-// once while both halves are wanted. The wave keeps four x-filtered chunks
+// Chunks go in pairs, requested together. A piece's pairs start at the
+// chunk before its first tile, so the pairs of a whole row (first tile 0)
+// start at odd chunks: where rows start on 128-byte boundaries a pair
+// covers the second half of one 128-byte line and the first half of the
+// next, and the two halves of a line are requested one pair apart, close
+// enough that the second request usually finds the first still in flight
+// and fetches the line again. Starting pairs at even chunks would add one
+// pair of x-filter work per piece. The wave keeps four x-filtered chunks
 // in a ring of register slots (the pair just filtered and the one before);
 // after each pair it filters the two z tiles that became complete. The pair
 // loop is unrolled by two, so every slot is static.
