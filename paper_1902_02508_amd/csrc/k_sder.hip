@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(T) k_sder(SderArgs g) {
         }
       }
       const float *D = g.D[(g.pmask >> f) & 1u];
-      if ((int)threadIdx.x < t.lim) {
+      if ((int)threadIdx.x < t.lim) {   // one thread per tile row (2P <= T, checked on the host)
         const int q = threadIdx.x;
         const int y = (int)((r0 + q) % g.ny);
         float d0 = 0.0f, d1, d2 = 0.0f, kind = 0.0f;   // kind: 0 interior, 1 y = 0, 2 y = ny - 1
@@ -956,15 +956,20 @@ hipError_t launch_sder(const GradView &v, bool zaxis, const float *ubar, float *
 }
 
 // LDS of the z kernel with the fused d/dy: 2P + 2 staged rows in the data
-// region (no more than 64 KB: the fused kernel is not given a larger limit)
+// region, the twiddles, and four floats of weights per tile row (no more
+// than 64 KB: the fused kernel is not given a larger limit)
 static size_t sder_dy_lds_bytes(const SderAxis &a) {
   return (size_t)((((a.P + 1) * a.n + 31) & ~31) + a.n) * 8 + (size_t)8 * a.P * 4;
+}
+
+bool sder_zy_ok(const GradView &v) {
+  return v.sz.nrad && v.sz.T == 256 && 2 * v.sz.P <= v.sz.T && v.ny >= 3 && sder_dy_lds_bytes(v.sz) <= 65536;
 }
 
 hipError_t launch_sder_zy(const GradView &v, const float *ubar, float *out, float *dy, long out_fstride,
                           unsigned pmask, hipStream_t s) {
   const SderAxis &a = v.sz;
-  if (!a.nrad || a.T != 256 || v.ny < 3 || sder_dy_lds_bytes(a) > 65536) return hipErrorInvalidValue;
+  if (!sder_zy_ok(v)) return hipErrorInvalidValue;
   SderArgs g;
   g.ax = a;
   g.in = ubar;
@@ -986,10 +991,6 @@ hipError_t launch_sder_zy(const GradView &v, const float *ubar, float *out, floa
   const SderKernel k = a.E == 16 ? sder_kernel_dy<16>(a) : sder_kernel_dy<32>(a);
   k<<<(unsigned)tiles, 256, sder_dy_lds_bytes(a), s>>>(g);
   return hipGetLastError();
-}
-
-bool sder_zy_ok(const GradView &v) {
-  return v.sz.nrad && v.sz.T == 256 && v.ny >= 3 && sder_dy_lds_bytes(v.sz) <= 65536;
 }
 
 hipError_t rfft_setup(const SderAxis &a, hipStream_t s) {
