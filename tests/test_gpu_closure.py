@@ -67,7 +67,10 @@ _PI = math.pi
     # and the other grids take it in its own kernel
     ("dns192", dict(nx=1024, ny=5, nz=768, delta_x=4 * _PI / 256, delta_z=2 * _PI / 192), False),
     ("dns192", dict(nx=4096, ny=3, nz=10, delta_x=4 * _PI / 1024, delta_z=2 * _PI / 4), False),
-    ("dns192", dict(nx=6, ny=3, nz=8192, delta_x=4 * _PI / 4, delta_z=2 * _PI / 2048), False)])
+    ("dns192", dict(nx=6, ny=3, nz=8192, delta_x=4 * _PI / 4, delta_z=2 * _PI / 2048), False),
+    # the production wall-normal grid (385 stretched rows) and z lines (768
+    # nodes) on a slab of eight x rows
+    ("dns1024", dict(nx=8), False)])
 def test_features_match_oracle(E, base, over, filtered):
     """Every feature against the oracle's FP64 gradient of the same FP32
     velocity, relative L2. Where the line length factors into 2, 3 and 5
