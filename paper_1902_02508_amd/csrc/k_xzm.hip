@@ -32,10 +32,10 @@
 // chunk before its first tile, so the pairs of a whole row (first tile 0)
 // start at odd chunks: where rows start on 128-byte boundaries a pair
 // covers the second half of one 128-byte line and the first half of the
-// next, and the two halves of a line are requested one pair apart, close
-// enough that the second request usually finds the first still in flight
-// and fetches the line again. Starting pairs at even chunks would add one
-// pair of x-filter work per piece. The wave keeps four x-filtered chunks
+// next, and the two halves of a line are requested one pair apart; by
+// then the line has usually left L2 (evicted mostly by the kernel's own
+// output stores), and it is fetched again. Starting pairs at even chunks
+// costs a pair per cut inside a row. The wave keeps four x-filtered chunks
 // in a ring of register slots (the pair just filtered and the one before);
 // after each pair it filters the two z tiles that became complete. The pair
 // loop is unrolled by two, so every slot is static.
