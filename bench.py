@@ -464,6 +464,59 @@ def measure_exact(cfg, ygemm, tail, xz, snapshots, steps, warmup, seeds, torch, 
                 roofs=roofs, dom=dom, passes=passes, matrix_xz=matrix_xz, ns=ns)
 
 
+def two_streams_block(cfg, a, m, torch, eles, log):
+    """The same exact path with snapshots alternating between two streams,
+    each with a filter handle of its own (a handle's per-call shift profile
+    is not shared between calls in flight), so that one snapshot's y pass
+    can run beside the next snapshot's x/z pass: steady-state throughput of
+    one and of two streams over the same resident snapshots (at least 200
+    snapshots each, the overlap needs a few to fill), and the outputs
+    compared bitwise with the one-stream run's."""
+    f, us = m["f"], m["us"]
+    dev = us[0].device
+    f2 = eles.Filter.from_config(cfg, tail_tol=a.tail, ygemm=a.ygemm, device=dev)
+    if f2.layout.xz_waves > 0:
+        f2.set_xz(m["matrix_xz"])
+    fs = [f, f2]
+    ns = len(us)
+    ub2 = [torch.empty_like(t) for t in m["ubar"]]
+    ta2 = [torch.empty_like(t) for t in m["tau"]]
+    st2 = [torch.empty_like(t) for t in m["stats"]]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+
+    def step(i):
+        # snapshot k, its outputs and its handle stay on stream k mod 2
+        k = i % ns
+        with torch.cuda.stream(streams[k % 2]):
+            fs[k % 2].sgs_stress(us[k], ub2[k], ta2[k], st2[k])
+
+    def one(i):
+        k = i % ns
+        f.sgs_stress(us[k], m["ubar"][k], m["tau"][k], m["stats"][k])
+
+    n = max(a.steps, 200)
+    el = {}
+    for name, fn in (("one", one), ("two", step)):
+        torch.cuda.synchronize()
+        for i in range(max(a.warmup, 4)):
+            fn(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n):
+            fn(i)
+        torch.cuda.synchronize()
+        el[name] = time.perf_counter() - t0
+    for k in range(ns):   # every snapshot once more on its own stream, then compare
+        step(k)
+    torch.cuda.synchronize()
+    same = all(torch.equal(x, y) for x, y in zip(m["ubar"] + m["tau"] + m["stats"], ub2 + ta2 + st2))
+    v1, v2 = cfg.points * n / el["one"], cfg.points * n / el["two"]
+    log(f"two streams: {1e3 * el['two'] / n:.4f} ms per snapshot (one stream {1e3 * el['one'] / n:.4f})")
+    return {"points_per_s": v2, "ms_per_snapshot": 1e3 * el["two"] / n, "one_stream_points_per_s": v1,
+            "speedup_vs_one_stream": v2 / v1, "snapshots_timed": n, "streams": 2, "handles": 2,
+            "bitwise_equal_to_one_stream": same}
+
+
 def production_block(a, torch, eles, synth, counters, np, log):
     """The production shape, 1024 x 385 x 768 (one snapshot resident in
     HBM): the exact path with the BF16x3 y pass (the configured production
@@ -592,6 +645,8 @@ def main():
         parity = max([R.rel_l2(gu[k], rub[k], yv) for k in range(3)] +
                      [R.rel_l2(gt[k], rtau[k], yv) for k in range(6)])
 
+    two = None if a.skip_extras else two_streams_block(cfg, a, m, torch, eles, log)
+
     head = {"value": m["value"], "ms_per_step": m["ms_per_step"], "roofline": m["roofs"][m["dom"]],
             "rooflines": m["roofs"], "passes": m["passes"], "matrix_xz": m["matrix_xz"], "ns": m["ns"],
             "layout": f.layout}
@@ -620,6 +675,7 @@ def main():
         "passes": head["passes"],
         "max_rel_l2_vs_oracle": parity,
         "les_grid": les,
+        "two_streams": two,
         "production": production,
         "closure": closure,
     }
