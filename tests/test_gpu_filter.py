@@ -282,6 +282,30 @@ def test_sgs_deterministic_and_invariants(E):
     assert tr.min() > -1e-6 * scale
 
 
+def test_two_handles_on_two_streams_match_one_stream(E):
+    """Snapshots alternating between two streams, each with a filter handle
+    of its own, give outputs bitwise equal to one handle on one stream (the
+    handles share no state; each snapshot's buffers stay on one stream)."""
+    import torch
+    cfg = synth.config("dns192", nx=48, nz=64)
+    us = [_dev(synth.make_snapshot(cfg, s)[1]) for s in (5, 6, 7, 8)]
+    fa = E.Filter.from_config(cfg, tail_tol=1e-8)
+    fb = E.Filter.from_config(cfg, tail_tol=1e-8)
+    ref = [[_host(t) for t in fa.sgs_stress(u)] for u in us]
+    outs = [[torch.empty((3,) + fa.shape, device="cuda"), torch.empty((6,) + fa.shape, device="cuda"),
+             torch.empty((9, cfg.ny), dtype=torch.float64, device="cuda")] for _ in us]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for k, u in enumerate(us):
+            with torch.cuda.stream(streams[k % 2]):
+                (fa, fb)[k % 2].sgs_stress(u, *outs[k])
+    torch.cuda.synchronize()
+    for k in range(len(us)):
+        for got, want in zip(outs[k], ref[k]):
+            assert np.array_equal(_host(got), want), k
+
+
 @pytest.mark.parametrize("mode", ["bf16x3", "bf16"])
 def test_sgs_reduced_precision_y_pass(E, mode):
     """The reduced-precision y arithmetics on the full 192 x 129 x 192
