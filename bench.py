@@ -304,9 +304,13 @@ def run_differential(a):
         roofs[k]["timed"] = "timed region" if k == dom else "per-pass loop"
     passes = {k: {"us_avg": 1e3 * ms / max(n, 1), "launches": n} for k, (ms, n) in prof_all.items()}
 
-    inverse, errors = None, None
+    inverse, errors, two = None, None, None
     if not a.skip_extras:
         inverse, errors = dfilter_extras(cfg, eles, torch, f, us, ubar, a.steps, counters)
+        f2 = eles.DFilter.from_config(cfg, a=0.1, device=dev)
+        two = two_streams_block(cfg, a, f, f2, us, ubar, tau, stats, torch,
+                                lambda msg: print(msg, file=sys.stderr, flush=True))
+        del f2
 
     cpu = None
     parity = None
@@ -320,7 +324,7 @@ def run_differential(a):
         gt = tau[0].cpu().numpy().astype(np.float64)
         parity = max([R.rel_l2(gu[k], rub[k], yv) for k in range(3)] +
                      [R.rel_l2(gt[k], rtau[k], yv) for k in range(6)])
-    return cfg, value, ms_per_step, ns, roofs, dom, passes, cpu, parity, inverse, errors
+    return cfg, value, ms_per_step, ns, roofs, dom, passes, cpu, parity, inverse, errors, two
 
 
 def dfilter_extras(cfg, eles, torch, f, us, ubar, steps, counters):
@@ -355,7 +359,7 @@ def dfilter_extras(cfg, eles, torch, f, us, ubar, steps, counters):
 
 
 def main_differential(a):
-    cfg, value, ms_per_step, ns, roofs, dom, passes, cpu, parity, inverse, errors = run_differential(a)
+    cfg, value, ms_per_step, ns, roofs, dom, passes, cpu, parity, inverse, errors, two = run_differential(a)
     line = {
         "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step,
@@ -372,6 +376,7 @@ def main_differential(a):
         "max_rel_l2_vs_oracle": parity,
         "inverse_filter": inverse,
         "errors_eq13_15": errors,
+        "two_streams": two,
     }
     print(json.dumps(line), flush=True)
 
@@ -464,24 +469,20 @@ def measure_exact(cfg, ygemm, tail, xz, snapshots, steps, warmup, seeds, torch, 
                 roofs=roofs, dom=dom, passes=passes, matrix_xz=matrix_xz, ns=ns)
 
 
-def two_streams_block(cfg, a, m, torch, eles, log):
+def two_streams_block(cfg, a, f, f2, us, ubar, tau, stats, torch, log):
     """The same exact path with snapshots alternating between two streams,
-    each with a filter handle of its own (a handle's per-call shift profile
-    is not shared between calls in flight), so that one snapshot's y pass
-    can run beside the next snapshot's x/z pass: steady-state throughput of
-    one and of two streams over the same resident snapshots (at least 200
-    snapshots each, the overlap needs a few to fill), and the outputs
-    compared bitwise with the one-stream run's."""
-    f, us = m["f"], m["us"]
-    dev = us[0].device
-    f2 = eles.Filter.from_config(cfg, tail_tol=a.tail, ygemm=a.ygemm, device=dev)
-    if f2.layout.xz_waves > 0:
-        f2.set_xz(m["matrix_xz"])
+    each with a filter handle of its own (f2 a second handle of f's
+    configuration: a handle's per-call state is not shared between calls in
+    flight), so that one snapshot's later passes can run beside the next
+    snapshot's first ones: steady-state throughput of one and of two streams
+    over the same resident snapshots (at least 200 snapshots each, the
+    overlap needs a few to fill), and the outputs compared bitwise with the
+    one-stream run's."""
     fs = [f, f2]
     ns = len(us)
-    ub2 = [torch.empty_like(t) for t in m["ubar"]]
-    ta2 = [torch.empty_like(t) for t in m["tau"]]
-    st2 = [torch.empty_like(t) for t in m["stats"]]
+    ub2 = [torch.empty_like(t) for t in ubar]
+    ta2 = [torch.empty_like(t) for t in tau]
+    st2 = [torch.empty_like(t) for t in stats]
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
 
     def step(i):
@@ -492,7 +493,7 @@ def two_streams_block(cfg, a, m, torch, eles, log):
 
     def one(i):
         k = i % ns
-        f.sgs_stress(us[k], m["ubar"][k], m["tau"][k], m["stats"][k])
+        f.sgs_stress(us[k], ubar[k], tau[k], stats[k])
 
     n = max(a.steps, 200)
     el = {}
@@ -506,10 +507,10 @@ def two_streams_block(cfg, a, m, torch, eles, log):
             fn(i)
         torch.cuda.synchronize()
         el[name] = time.perf_counter() - t0
-    for k in range(ns):   # every snapshot once more on its own stream, then compare
-        step(k)
-    torch.cuda.synchronize()
-    same = all(torch.equal(x, y) for x, y in zip(m["ubar"] + m["tau"] + m["stats"], ub2 + ta2 + st2))
+    # both loops covered every snapshot (n >= ns), one after the other, so
+    # ubar/tau/stats hold the one-stream outputs and ub2/ta2/st2 the
+    # two-stream ones; f is never used on two streams at once
+    same = all(torch.equal(x, y) for x, y in zip(ubar + tau + stats, ub2 + ta2 + st2))
     v1, v2 = cfg.points * n / el["one"], cfg.points * n / el["two"]
     log(f"two streams: {1e3 * el['two'] / n:.4f} ms per snapshot (one stream {1e3 * el['one'] / n:.4f})")
     return {"points_per_s": v2, "ms_per_snapshot": 1e3 * el["two"] / n, "one_stream_points_per_s": v1,
@@ -645,7 +646,13 @@ def main():
         parity = max([R.rel_l2(gu[k], rub[k], yv) for k in range(3)] +
                      [R.rel_l2(gt[k], rtau[k], yv) for k in range(6)])
 
-    two = None if a.skip_extras else two_streams_block(cfg, a, m, torch, eles, log)
+    two = None
+    if not a.skip_extras:
+        f2 = eles.Filter.from_config(cfg, tail_tol=a.tail, ygemm=a.ygemm, device=dev)
+        if f2.layout.xz_waves > 0:
+            f2.set_xz(m["matrix_xz"])
+        two = two_streams_block(cfg, a, f, f2, us, ubar, tau, stats, torch, log)
+        del f2
 
     head = {"value": m["value"], "ms_per_step": m["ms_per_step"], "roofline": m["roofs"][m["dom"]],
             "rooflines": m["roofs"], "passes": m["passes"], "matrix_xz": m["matrix_xz"], "ns": m["ns"],
