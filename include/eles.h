@@ -39,7 +39,12 @@
  * the operators' band structure back to plan the y pass), closure_create,
  * closure_get_params / closure_set_params, and closure_infer in its
  * checked modes. One handle must not be used from two streams or threads
- * at once. All device pointers must be 16-byte aligned.
+ * at once (a call keeps per-call data, such as the shift profile of the
+ * stress, in the handle's state). Separate handles of the same
+ * configuration share nothing: snapshots alternating between two streams,
+ * each with its own handle and output buffers, give results bitwise equal
+ * to one handle on one stream, and let one call's later passes overlap the
+ * next call's first ones. All device pointers must be 16-byte aligned.
  *
  * Errors. Arguments are validated before anything is enqueued; a failing
  * validation returns a non-zero eles_status and enqueues nothing. A HIP
